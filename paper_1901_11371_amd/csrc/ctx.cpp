@@ -1,0 +1,455 @@
+// Device context: construction upload, leaf factorisation, and the matvec /
+// preconditioner entry points of the C ABI.
+#include "ctx.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+
+using namespace hbf;
+
+namespace {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+void dmalloc(T** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    throw std::bad_alloc();
+  }
+  (void)what;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void free_device(hbf_ctx* c) {
+  dfree(c->d_fac);
+  dfree(c->d_perm);
+  dfree(c->d_units);
+  dfree(c->d_gofs);
+  dfree(c->d_gunits);
+  dfree(c->d_arena);
+  dfree(c->d_vin);
+  dfree(c->d_vout);
+  dfree(c->d_u);
+  dfree(c->d_t);
+  dfree(c->d_diag64);
+  dfree(c->d_flag);
+  dfree(c->d_krylov);
+  dfree(c->d_w);
+  dfree(c->d_x64);
+  dfree(c->d_red);
+  dfree(c->d_small);
+  c->d_fac = c->d_arena = c->d_vin = c->d_vout = c->d_u = c->d_t = nullptr;
+  c->d_krylov = c->d_w = c->d_x64 = nullptr;
+}
+
+// Upload host complex128 entries [begin, end) of P.fac as the storage dtype.
+void upload_factors(hbf_ctx* c, int64_t begin, int64_t end, hipStream_t s) {
+  const size_t chunk = size_t(1) << 22;  // entries per staging transfer
+  void* stage = nullptr;
+  hip_check(hipHostMalloc(&stage, chunk * c->elt, hipHostMallocDefault), "hipHostMalloc");
+  try {
+    for (int64_t e = begin; e < end; e += static_cast<int64_t>(chunk)) {
+      const int64_t m = std::min<int64_t>(static_cast<int64_t>(chunk), end - e);
+      if (c->dtype == HBF_C64) {
+        float* f = static_cast<float*>(stage);
+        for (int64_t i = 0; i < m; ++i) {
+          f[2 * i] = static_cast<float>(c->P.fac[e + i].real());
+          f[2 * i + 1] = static_cast<float>(c->P.fac[e + i].imag());
+        }
+      } else {
+        std::memcpy(stage, &c->P.fac[e], m * 16);
+      }
+      hip_check(hipMemcpyAsync(static_cast<char*>(c->d_fac) + e * c->elt, stage, m * c->elt,
+                               hipMemcpyHostToDevice, s),
+                "upload factors");
+      hip_check(hipStreamSynchronize(s), "upload sync");
+    }
+  } catch (...) {
+    (void)hipHostFree(stage);
+    throw;
+  }
+  (void)hipHostFree(stage);
+}
+
+// FP64 leaf blocks with the current impedance -> device, and factorise them.
+void factor_leaves(hbf_ctx* c, hipStream_t s) {
+  if (c->prec == HBF_PREC_NONE || c->P.leaf_fwd_unit.empty()) return;
+  const int n0 = c->P.n0;
+  const int64_t nl = c->n / n0;
+  const int64_t bs = static_cast<int64_t>(n0) * n0;
+  std::vector<cd> D(c->diag_noz.size());
+  for (int64_t b = 0; b < nl; ++b) {
+    for (int64_t e = 0; e < bs; ++e) D[b * bs + e] = c->diag_noz[b * bs + e];
+    if (!c->P.z.empty())
+      for (int i = 0; i < n0; ++i) {
+        cd& d = D[b * bs + static_cast<int64_t>(i) * n0 + i];
+        d.x += c->P.z[b * n0 + i].real();
+        d.y += c->P.z[b * n0 + i].imag();
+      }
+  }
+  hip_check(hipMemcpyAsync(c->d_diag64, D.data(), D.size() * sizeof(cd), hipMemcpyHostToDevice, s), "upload leaves");
+  hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int), s), "memset flag");
+  const int64_t batch = std::min<int64_t>(nl, 1024);
+  cd* work = nullptr;
+  dmalloc(&work, static_cast<size_t>(batch) * 2 * bs * sizeof(cd), "leaf work");
+  try {
+    const Unit& uf = c->P.units[c->P.leaf_fwd_unit[0]];
+    const Unit& ub = c->P.units[c->P.leaf_bwd_unit[0]];
+    const int64_t stride = uf.mat_len;
+    const int mode = (c->prec == HBF_PREC_PAPER_TRI) ? 1 : 0;
+    for (int64_t b0 = 0; b0 < nl; b0 += batch) {
+      const int64_t nb = std::min(batch, nl - b0);
+      hip_check(launch_leaf_factor(c->d_diag64, b0, nb, n0, mode, c->P.scale.real(), c->P.scale.imag(), c->d_fac,
+                                   c->dtype == HBF_C128, uf.mat, ub.mat, stride, c->d_flag, work, s),
+                "leaf factor");
+    }
+    int flag = 0;
+    hip_check(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s), "flag");
+    hip_check(hipStreamSynchronize(s), "leaf sync");
+    dfree(work);
+    work = nullptr;
+    if (flag) throw std::domain_error("a leaf block is singular to working precision");
+  } catch (...) {
+    dfree(work);
+    throw;
+  }
+}
+
+hbf_status fail(hbf_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+}  // namespace
+
+namespace hbf {
+
+hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
+                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s) {
+  const size_t szA = (vec_c128 || c->dtype == HBF_C128) ? 16 : 8;
+  const size_t szF = c->elt;
+  const int ch_cap = static_cast<int>(32768 / szF);
+  for (const Launch& l : L) {
+    StageArgs a;
+    a.units = c->d_units;
+    a.gofs = c->d_gofs;
+    a.gunits = c->d_gunits;
+    a.fac = c->d_fac;
+    a.perm = c->d_perm;
+    a.buf[BUF_X] = X;
+    a.buf[BUF_Y] = Y;
+    a.buf[BUF_ARENA] = c->d_arena;
+    a.first = l.first;
+    a.direct = l.direct;
+    a.R = R;
+    const int md = std::max(1, l.max_dst);
+    int rc = std::min(R, std::max(1, (kStageThreads * kOutPerThread) / md));
+    while (rc > 1 && static_cast<size_t>(l.max_src) * rc * szA > 24576) --rc;
+    a.rc = rc;
+    a.nchunks = (R + rc - 1) / rc;
+    a.acc = l.out_leaf;
+    a.alpha_re = alpha_re;
+    a.alpha_im = alpha_im;
+    int ch = std::min(ch_cap, (l.max_mat + 1) & ~1);
+    if (ch < 2) ch = 2;
+    a.ch = ch;
+    a.src_cap = std::max(1, l.max_src * rc);
+    const size_t lds = static_cast<size_t>(a.src_cap) * szA + static_cast<size_t>(ch) * szF + 1024;
+    hipError_t e;
+    if (c->dtype == HBF_C128) e = launch_stage_c128(a, l.count, adjoint, lds, s);
+    else if (vec_c128) e = launch_stage_c64_hi(a, l.count, adjoint, lds, s);
+    else e = launch_stage_c64(a, l.count, adjoint, lds, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s) {
+  hipError_t e;
+  if (!adjoint) e = run_launches(c, c->P.mv_fwd, false, xin, yout, R, vec_c128, 1.0, 0.0, s);
+  else e = run_launches(c, c->P.mv_adj, true, yout, xin, R, vec_c128, 1.0, 0.0, s);
+  if (e != hipSuccess) return fail(HBF_EHIP, std::string("matvec launch: ") + hipGetErrorString(e));
+  return HBF_OK;
+}
+
+// z = P^{-1} r (or P^{-H} r); r, z internal layout, vector dtype = context dtype.
+hbf_status precond_internal(hbf_ctx* c, const void* rin, void* zout, int R, bool adjoint, hipStream_t s) {
+  const size_t bytes = static_cast<size_t>(c->n) * R * c->elt;
+  hipError_t e = hipMemcpyAsync(c->d_u, rin, bytes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(HBF_EHIP, "precond copy");
+  if (c->prec == HBF_PREC_NONE) {
+    e = hipMemcpyAsync(zout, c->d_u, bytes, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? HBF_OK : fail(HBF_EHIP, "precond copy");
+  }
+  const bool paper = c->prec == HBF_PREC_PAPER_TRI;
+  const double are = paper ? c->P.scale.real() : 1.0, aim = paper ? c->P.scale.imag() : 0.0;
+  const bool v128 = c->dtype == HBF_C128;
+  if (!adjoint) {
+    e = run_launches(c, c->S.fwd, false, c->d_t, c->d_u, R, v128, -are, -aim, s);
+    if (e == hipSuccess) {
+      void* mid = paper ? c->d_t : c->d_u;
+      e = run_launches(c, c->S.bwd, false, zout, mid, R, v128, -1.0, 0.0, s);
+    }
+  } else {
+    e = run_launches(c, c->S.adj_fwd, true, c->d_u, c->d_t, R, v128, -1.0, 0.0, s);
+    if (e == hipSuccess) {
+      void* mid = paper ? c->d_t : c->d_u;
+      e = run_launches(c, c->S.adj_bwd, true, mid, zout, R, v128, -are, aim, s);
+    }
+  }
+  if (e != hipSuccess) return fail(HBF_EHIP, std::string("precond launch: ") + hipGetErrorString(e));
+  return HBF_OK;
+}
+
+}  // namespace hbf
+
+extern "C" {
+
+hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double tol, const hbf_build_opts* opts,
+                     hbf_ctx** out) {
+  if (!out) return fail(HBF_EINVAL, "hbf_build: out is NULL");
+  *out = nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<hbf_ctx> c(new (std::nothrow) hbf_ctx());
+  if (!c) return fail(HBF_ENOMEM, "hbf_build: out of host memory");
+  hipStream_t s = nullptr;
+  try {
+    c->dtype = opts ? opts->dtype : HBF_C64;
+    c->prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
+    if (c->dtype != HBF_C64 && c->dtype != HBF_C128) return fail(HBF_EINVAL, "hbf_build: bad dtype");
+    if (c->prec != HBF_PREC_BLOCK_LU && c->prec != HBF_PREC_PAPER_TRI && c->prec != HBF_PREC_NONE)
+      return fail(HBF_EINVAL, "hbf_build: bad preconditioner");
+    if (leaf > 64) return fail(HBF_EINVAL, "hbf_build: the device path supports leaf <= 64");
+    c->max_nrhs = (opts && opts->max_nrhs > 0) ? opts->max_nrhs : 1;
+    c->restart = (opts && opts->restart > 0) ? opts->restart : 30;
+    c->device = opts ? opts->device : 0;
+    c->elt = c->dtype == HBF_C64 ? 8 : 16;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+      (void)hipGetLastError();
+      return fail(HBF_EHIP, "hbf_build: no HIP device");
+    }
+    if (c->device < 0 || c->device >= ndev) return fail(HBF_EINVAL, "hbf_build: bad device ordinal");
+    hip_check(hipSetDevice(c->device), "hipSetDevice");
+    hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+
+    build_plan(c->P, curve, kappa, leaf, tol, opts);
+    build_sweeps(c->P, c->S);
+    Plan& P = c->P;
+    c->n = P.n;
+    const int64_t N = P.n;
+    const int n0 = P.n0;
+    const int64_t nl = N / n0;
+    const int64_t bs = static_cast<int64_t>(n0) * n0;
+    // keep FP64 leaf blocks without z for refactoring
+    c->diag_noz.resize(static_cast<size_t>(nl * bs));
+    for (int64_t b = 0; b < nl; ++b) {
+      const Unit& u = P.units[P.diag_unit[b]];
+      for (int64_t e = 0; e < bs; ++e) {
+        cplx v = P.fac[u.mat + e];
+        c->diag_noz[b * bs + e] = cd{v.real(), v.imag()};
+      }
+      if (!P.z.empty())
+        for (int i = 0; i < n0; ++i) {
+          cd& d = c->diag_noz[b * bs + static_cast<int64_t>(i) * n0 + i];
+          d.x -= P.z[b * n0 + i].real();
+          d.y -= P.z[b * n0 + i].imag();
+        }
+    }
+    const int64_t fac_entries = P.leaf_fac_begin + P.leaf_fac_len;
+    dmalloc(&c->d_fac, static_cast<size_t>(fac_entries) * c->elt, "factors");
+    upload_factors(c.get(), 0, P.leaf_fac_begin, s);
+    dmalloc(&c->d_perm, P.perm.size() + 16, "perm");
+    if (!P.perm.empty())
+      hip_check(hipMemcpy(c->d_perm, P.perm.data(), P.perm.size(), hipMemcpyHostToDevice), "upload perm");
+    dmalloc(&c->d_units, P.units.size() * sizeof(Unit), "units");
+    hip_check(hipMemcpy(c->d_units, P.units.data(), P.units.size() * sizeof(Unit), hipMemcpyHostToDevice), "units");
+    dmalloc(&c->d_gofs, P.group_off.size() * sizeof(int32_t), "groups");
+    hip_check(hipMemcpy(c->d_gofs, P.group_off.data(), P.group_off.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+              "groups");
+    dmalloc(&c->d_gunits, P.group_units.size() * sizeof(int32_t), "groups");
+    hip_check(hipMemcpy(c->d_gunits, P.group_units.data(), P.group_units.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice),
+              "groups");
+    const size_t R = static_cast<size_t>(c->max_nrhs);
+    const size_t vbytes = static_cast<size_t>(N) * R * 16;
+    dmalloc(&c->d_arena, static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16, "arena");
+    dmalloc(&c->d_vin, vbytes, "vectors");
+    dmalloc(&c->d_vout, vbytes, "vectors");
+    dmalloc(&c->d_u, vbytes, "vectors");
+    dmalloc(&c->d_t, vbytes, "vectors");
+    dmalloc(&c->d_diag64, static_cast<size_t>(nl * bs) * sizeof(cd), "leaves");
+    dmalloc(&c->d_flag, 256, "flag");
+    // solver workspace (inner Krylov basis in the context dtype, FP64 outer vectors)
+    dmalloc(&c->d_krylov, static_cast<size_t>(c->restart + 1) * N * R * c->elt, "krylov");
+    dmalloc(&c->d_w, static_cast<size_t>(N) * R * c->elt, "krylov");
+    dmalloc(&c->d_x64, 4 * vbytes, "solver vectors");
+    c->red_len = static_cast<size_t>(2 * (c->restart + 2)) * R * 1024;
+    dmalloc(&c->d_red, c->red_len * sizeof(double), "reduction");
+    dmalloc(&c->d_small, static_cast<size_t>(R) * 8 * (c->restart + 2) * (c->restart + 2) * sizeof(double),
+            "hessenberg");
+    c->workspace_bytes = static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16 + 4 * vbytes +
+                         static_cast<size_t>(c->restart + 2) * N * R * c->elt + 4 * vbytes;
+    factor_leaves(c.get(), s);
+    // release the host copies of the factors
+    fill_stats(P, &c->stats, c->elt);
+    c->stats.bytes_index = static_cast<int64_t>(P.perm.size() + P.units.size() * sizeof(Unit));
+    std::vector<cplx>().swap(P.fac);
+    hip_check(hipStreamSynchronize(s), "build sync");
+    (void)hipStreamDestroy(s);
+    s = nullptr;
+    c->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->stats.build_seconds = c->build_seconds;
+    c->stats.bytes_workspace = static_cast<int64_t>(c->workspace_bytes);
+    *out = c.release();
+    return HBF_OK;
+  } catch (const std::invalid_argument& e) {
+    if (s) (void)hipStreamDestroy(s);
+    free_device(c.get());
+    return fail(HBF_EINVAL, e.what());
+  } catch (const std::bad_alloc&) {
+    if (s) (void)hipStreamDestroy(s);
+    free_device(c.get());
+    return fail(HBF_ENOMEM, "hbf_build: out of memory");
+  } catch (const std::domain_error& e) {
+    if (s) (void)hipStreamDestroy(s);
+    free_device(c.get());
+    return fail(HBF_ESINGULAR, e.what());
+  } catch (const std::exception& e) {
+    if (s) (void)hipStreamDestroy(s);
+    free_device(c.get());
+    return fail(HBF_EHIP, e.what());
+  }
+}
+
+hbf_status hbf_set_impedance(hbf_ctx* c, const double* z) {
+  if (!c || !z) return fail(HBF_EINVAL, "hbf_set_impedance: NULL argument");
+  for (int64_t i = 0; i < 2 * c->n; ++i)
+    if (!std::isfinite(z[i])) return fail(HBF_EINVAL, "hbf_set_impedance: non-finite impedance");
+  try {
+    hip_check(hipSetDevice(c->device), "hipSetDevice");
+    c->P.z.resize(c->n);
+    for (int64_t i = 0; i < c->n; ++i) c->P.z[i] = cplx(z[2 * i], z[2 * i + 1]);
+    // refresh the dense diagonal units used by the matvec (their matrices hold A_bb)
+    const int n0 = c->P.n0;
+    const int64_t nl = c->n / n0;
+    const int64_t bs = static_cast<int64_t>(n0) * n0;
+    std::vector<cd> D(static_cast<size_t>(nl * bs));
+    for (int64_t b = 0; b < nl; ++b) {
+      for (int64_t e = 0; e < bs; ++e) D[b * bs + e] = c->diag_noz[b * bs + e];
+      for (int i = 0; i < n0; ++i) {
+        cd& d = D[b * bs + static_cast<int64_t>(i) * n0 + i];
+        d.x += c->P.z[b * n0 + i].real();
+        d.y += c->P.z[b * n0 + i].imag();
+      }
+    }
+    // the rescaling follows the largest diagonal entry
+    {
+      int64_t ib = 0;
+      double best = -1.0;
+      for (int64_t i = 0; i < c->n; ++i) {
+        const cd& d = D[(i / n0) * bs + (i % n0) * n0 + (i % n0)];
+        const double m = std::hypot(d.x, d.y);
+        if (m > best) { best = m; ib = i; }
+      }
+      const cd& d = D[(ib / n0) * bs + (ib % n0) * n0 + (ib % n0)];
+      c->P.scale = 1.0 / cplx(d.x, d.y);
+    }
+    hipStream_t s = nullptr;
+    for (int64_t b = 0; b < nl; ++b) {
+      const Unit& u = c->P.units[c->P.diag_unit[b]];
+      if (c->dtype == HBF_C64) {
+        std::vector<float> f(2 * bs);
+        for (int64_t e = 0; e < bs; ++e) {
+          f[2 * e] = static_cast<float>(D[b * bs + e].x);
+          f[2 * e + 1] = static_cast<float>(D[b * bs + e].y);
+        }
+        hip_check(hipMemcpy(static_cast<char*>(c->d_fac) + u.mat * c->elt, f.data(), bs * 8, hipMemcpyHostToDevice),
+                  "diag upload");
+      } else {
+        hip_check(hipMemcpy(static_cast<char*>(c->d_fac) + u.mat * c->elt, &D[b * bs], bs * 16,
+                            hipMemcpyHostToDevice),
+                  "diag upload");
+      }
+    }
+    factor_leaves(c, s);
+    c->stats.scale_re = c->P.scale.real();
+    c->stats.scale_im = c->P.scale.imag();
+    return HBF_OK;
+  } catch (const std::domain_error& e) {
+    return fail(HBF_ESINGULAR, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HBF_ENOMEM, "hbf_set_impedance: out of memory");
+  } catch (const std::exception& e) {
+    return fail(HBF_EHIP, e.what());
+  }
+}
+
+hbf_status hbf_matvec(hbf_ctx* c, const void* x, void* y, int32_t nrhs, hbf_dtype io, int32_t adjoint, void* stream) {
+  if (!c || !x || !y) return fail(HBF_EINVAL, "hbf_matvec: NULL argument");
+  if (nrhs < 1 || nrhs > c->max_nrhs) return fail(HBF_EINVAL, "hbf_matvec: nrhs out of range [1, max_nrhs]");
+  if (io != HBF_C64 && io != HBF_C128) return fail(HBF_EINVAL, "hbf_matvec: bad io dtype");
+  if (c->dtype == HBF_C128 && io == HBF_C64) return fail(HBF_EINVAL, "hbf_matvec: complex64 io on a complex128 context");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(HBF_EHIP, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool v128 = io == HBF_C128;
+  if (nrhs == 1) return matvec_internal(c, const_cast<void*>(x), y, 1, v128, adjoint != 0, s);
+  if (launch_to_internal(x, v128, c->d_vin, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  hbf_status st = matvec_internal(c, c->d_vin, c->d_vout, nrhs, v128, adjoint != 0, s);
+  if (st != HBF_OK) return st;
+  if (launch_to_external(c->d_vout, v128, y, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  return HBF_OK;
+}
+
+hbf_status hbf_precond_apply(hbf_ctx* c, const void* r, void* z, int32_t nrhs, hbf_dtype io, int32_t adjoint,
+                             void* stream) {
+  if (!c || !r || !z) return fail(HBF_EINVAL, "hbf_precond_apply: NULL argument");
+  if (nrhs < 1 || nrhs > c->max_nrhs) return fail(HBF_EINVAL, "hbf_precond_apply: nrhs out of range");
+  if (io != c->dtype) return fail(HBF_EINVAL, "hbf_precond_apply: io dtype must equal the context dtype");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(HBF_EHIP, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool v128 = io == HBF_C128;
+  if (nrhs == 1) return precond_internal(c, r, z, 1, adjoint != 0, s);
+  if (launch_to_internal(r, v128, c->d_vin, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  hbf_status st = precond_internal(c, c->d_vin, c->d_vout, nrhs, adjoint != 0, s);
+  if (st != HBF_OK) return st;
+  if (launch_to_external(c->d_vout, v128, z, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  return HBF_OK;
+}
+
+hbf_status hbf_stats(const hbf_ctx* c, hbf_stats_t* out) {
+  if (!c || !out) return fail(HBF_EINVAL, "hbf_stats: NULL argument");
+  *out = c->stats;
+  return HBF_OK;
+}
+
+int64_t hbf_size(const hbf_ctx* c) { return c ? c->n : -1; }
+
+void hbf_free(hbf_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  free_device(c);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Device context of the H-IDBF-LU library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "hbf_internal.h"
+#include "kernels.h"
+#include "schedule.h"
+
+struct hbf_ctx {
+  hbf::Plan P;       // host plan (factor entries released after upload)
+  hbf::Sweeps S;
+  hbf_dtype dtype = HBF_C64;
+  hbf_prec prec = HBF_PREC_BLOCK_LU;
+  int device = 0;
+  int max_nrhs = 1;
+  int restart = 30;
+  int64_t n = 0;
+  int elt = 8;                 // bytes per factor entry
+
+  // device memory
+  void* d_fac = nullptr;       // factors + leaf inverses (storage dtype)
+  uint8_t* d_perm = nullptr;
+  hbf::Unit* d_units = nullptr;
+  int32_t* d_gofs = nullptr;
+  int32_t* d_gunits = nullptr;
+  void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
+  void* d_vin = nullptr;       // internal-layout vectors, N x max_nrhs x 16 bytes each
+  void* d_vout = nullptr;
+  void* d_u = nullptr;         // preconditioner work
+  void* d_t = nullptr;
+  hbf::cd* d_diag64 = nullptr; // FP64 diagonal leaf blocks (with z), column-major
+  int* d_flag = nullptr;
+  // solver workspace
+  void* d_krylov = nullptr;    // (restart+1) Krylov vectors, N x max_nrhs, inner dtype
+  void* d_w = nullptr;         // one work vector (inner dtype)
+  void* d_x64 = nullptr;       // FP64 outer vectors: x, r, b, d (N x max_nrhs each)
+  double* d_red = nullptr;     // reduction scratch
+  double* d_small = nullptr;   // Hessenberg / Givens state
+  size_t red_len = 0;
+
+  std::vector<hbf::cd> diag_noz;  // host FP64 leaf blocks without z (for set_impedance)
+  hbf_stats_t stats{};
+  double build_seconds = 0;
+  size_t workspace_bytes = 0;
+};
+
+namespace hbf {
+
+// Run a schedule on the device.  vec_c128: vectors are complex128 (with
+// complex64 factors this selects FP64 accumulation).
+hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
+                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s);
+
+hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s);
+hbf_status precond_internal(hbf_ctx* c, const void* rin, void* zout, int R, bool adjoint, hipStream_t s);
+
+}  // namespace hbf

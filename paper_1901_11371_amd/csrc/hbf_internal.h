@@ -1,0 +1,141 @@
+// Internal data structures of the H-IDBF-LU library (host side and the layout
+// shared with the device kernels).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hbf.h"
+
+namespace hbf {
+
+using cplx = std::complex<double>;
+
+cplx hankel2_0(double x);
+
+void set_error(const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// One "unit": a small dense operation of the factor chain of one butterfly
+// block (or a dense leaf block).  All units are stored in one table that the
+// device kernels read directly, so the layout is fixed (64 bytes).
+//
+// Forward semantics, with src = concatenation of the input segments and
+// dst = concatenation of the output segments:
+//   GATHER  (column-ID transfer, the V factors):   two IDs a, b with ranks
+//           k[0], k[1] = out_len[0], out_len[1]:
+//             out_o[i] = src[perm_o[i]] + sum_t T_o(i, t) src[perm_o[k_o + t]]
+//           T_o is k_o x (n_src - k_o), stored column-major; perm_o has n_src
+//           bytes (skeleton positions first).
+//   SCATTER (row-ID transfer, the U factors):       two IDs with ranks
+//           k[0], k[1] = in_len[0], in_len[1]:
+//             dst += Lambda_o [I; T_o^T] in_o, i.e. for q = invperm_o[p]:
+//             dst[p] += (q < k_o) ? in_o[q] : sum_j T_o(j, q - k_o) in_o[j]
+//           T_o is k_o x (n_dst - k_o), stored row-major; invperm_o has n_dst
+//           bytes.
+//   DENSE   dst = M src, M n_dst x n_src stored column-major.
+// Adjoint semantics swap the roles of the input and output segments and use
+// conjugate-transposed matrices.
+// ---------------------------------------------------------------------------
+enum UnitType : uint8_t { UNIT_GATHER = 0, UNIT_SCATTER = 1, UNIT_DENSE = 2 };
+enum BufId : uint8_t { BUF_X = 0, BUF_Y = 1, BUF_ARENA = 2 };
+
+struct alignas(16) Unit {
+  int64_t mat;         // offset (complex entries) of the unit's matrices in the factor array
+  int64_t perm;        // byte offset of the unit's permutations
+  int32_t in_off[2];   // row offsets of the input segments
+  int32_t out_off[2];  // row offsets of the output segments
+  int16_t in_len[2];   // lengths (0 = absent)
+  int16_t out_len[2];
+  int16_t k[2];        // ranks of the two IDs (GATHER/SCATTER)
+  uint8_t type;
+  uint8_t in_buf;      // BufId of the input segments
+  uint8_t out_buf;     // BufId of the output segments
+  uint8_t pad0;
+  int32_t mat_len;     // complex entries of the unit's matrices (padded to even)
+  int32_t pad1[3];
+};
+static_assert(sizeof(Unit) == 64, "Unit must be 64 bytes");
+
+// A launch of the stage kernel: a range of groups; a group is a list of units
+// whose outputs cover the same rows and are summed (direct=1: each group is
+// the single unit unit_begin + g).
+struct Launch {
+  int32_t direct;
+  int32_t first;       // first group (or first unit when direct)
+  int32_t count;       // number of groups
+  int32_t max_src;     // largest source length of any unit in the launch
+  int32_t max_dst;
+  int32_t max_mat;     // largest matrix (complex entries) of any unit
+  int32_t out_leaf;    // 1 if the launch writes rows of the external vector (uses alpha/beta)
+  int32_t kind;        // 0 butterfly/dense, 1 leaf solve
+};
+
+// Per-butterfly-block bookkeeping.
+struct BlockInfo {
+  int64_t row0, col0, n;
+  int L, D;
+  int hlevel;          // v (1-based); the pair is the diagonal node (v-1, pair)
+  int64_t pair;
+  int lower;           // 1: F21 (rows = second child), 0: F12
+  // unit ranges of the 2D+1 block levels, in forward order
+  std::vector<int32_t> lvl_begin, lvl_end;
+};
+
+// The whole host-side factorisation.
+struct Plan {
+  // problem
+  int64_t n = 0;
+  int n0 = 0;
+  int V = 0;                 // log2(N / n0)
+  double kappa = 0, eta0 = 0, tol = 0;
+  std::vector<double> cx, cy, w;  // segment centres and lengths
+  std::vector<cplx> z;            // per-unknown impedance (may be empty)
+  cplx scale = 1.0;               // a = 1/A[i*,i*]
+
+  // factors
+  std::vector<Unit> units;
+  std::vector<cplx> fac;          // all unit matrices, FP64
+  std::vector<uint8_t> perm;      // all permutations
+  int64_t arena_rows = 0;
+  std::vector<BlockInfo> blocks;
+  // dense units: diag_unit[b] (A_bb), l0_unit[pair at level V] (lower and upper)
+  std::vector<int32_t> diag_unit;
+  std::vector<int32_t> l0_lower_unit, l0_upper_unit;  // per pair of the last level
+  // leaf-solve units (matrices filled on the device; host holds only the layout)
+  std::vector<int32_t> leaf_fwd_unit, leaf_bwd_unit;
+  int64_t leaf_fac_begin = 0;     // first complex entry of the leaf-inverse region
+  int64_t leaf_fac_len = 0;
+
+  // matvec schedules (forward and adjoint): launches over group tables
+  std::vector<int32_t> group_off, group_units;
+  std::vector<Launch> mv_fwd, mv_adj;
+
+  // stats
+  int max_rank = 0;
+  double sum_rank = 0;
+  int64_t n_ids = 0;
+  int64_t bytes_butterfly_c128 = 0, bytes_dense_c128 = 0;
+  double build_seconds = 0;
+
+  cplx entry(int64_t i, int64_t j) const;
+  cplx self_entry(int64_t i) const;
+};
+
+// Build the plan (host only).  Throws std::runtime_error on invalid input.
+void build_plan(Plan& p, const hbf_curve* curve, double kappa, int leaf, double tol,
+                const hbf_build_opts* opts);
+
+// Host FP64 evaluation of the plan: y = A x or A^H x for nrhs vectors
+// (x, y are (nrhs, N) complex128).
+void plan_apply(const Plan& p, const cplx* x, cplx* y, int nrhs, bool adjoint);
+
+// Add a group of units to a group table; returns the group index.
+int32_t add_group(Plan& p, const std::vector<int32_t>& unit_ids);
+
+// Number of worker threads for the construction.
+int build_threads(const hbf_build_opts* opts);
+
+}  // namespace hbf

@@ -1,0 +1,452 @@
+// Sweep schedules (block forward / back substitution of Algorithms 3 and 4
+// over the H-IDBF), the FP64 host executor of any schedule, the host leaf
+// factorisation used by the construction checks, and the host-only C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+
+#include "hbf_internal.h"
+#include "schedule.h"
+
+namespace hbf {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Sweeps.  The recursion over the diagonal tree follows Algorithm 3 (lower:
+// first child, then the off-diagonal update of the second child, then the
+// second child) and Algorithm 4 (upper: second child first).  For the
+// adjoint preconditioner the systems are conjugate-transposed, so the lower
+// sweep uses the upper blocks F12^H and the upper sweep the lower blocks
+// F21^H, each traversed in reverse factor order.
+// ---------------------------------------------------------------------------
+static void sweep_rec(const Plan& P, const std::vector<int>& level_base, int dd, int64_t idx,
+                      bool lower_dir, bool adjoint, const std::vector<int32_t>& leaf_units,
+                      std::vector<Launch>& out) {
+  auto push = [&](int32_t u0, int32_t u1, int acc, int kind) {
+    Launch l;
+    l.direct = 1;
+    l.first = u0;
+    l.count = u1 - u0;
+    l.max_src = l.max_dst = l.max_mat = 0;
+    for (int32_t u = u0; u < u1; ++u) {
+      const Unit& q = P.units[u];
+      const int a = q.in_len[0] + q.in_len[1], b = q.out_len[0] + q.out_len[1];
+      l.max_src = std::max({l.max_src, a, b});
+      l.max_dst = std::max({l.max_dst, a, b});
+      l.max_mat = std::max<int32_t>(l.max_mat, q.mat_len);
+    }
+    l.out_leaf = acc;
+    l.kind = kind;
+    out.push_back(l);
+  };
+  if (dd == P.V) {
+    push(leaf_units[idx], leaf_units[idx] + 1, 0, 1);
+    return;
+  }
+  const int64_t first = lower_dir ? 2 * idx : 2 * idx + 1;
+  const int64_t second = lower_dir ? 2 * idx + 1 : 2 * idx;
+  sweep_rec(P, level_base, dd + 1, first, lower_dir, adjoint, leaf_units, out);
+  const bool use_lower = (lower_dir != adjoint);
+  if (dd + 1 == P.V) {
+    const int32_t u = use_lower ? P.l0_lower_unit[idx] : P.l0_upper_unit[idx];
+    push(u, u + 1, 1, 0);
+  } else {
+    const BlockInfo& bi = P.blocks[level_base[dd + 1] + 2 * idx + (use_lower ? 1 : 0)];
+    const int nl = 2 * bi.D + 1;
+    for (int s = 0; s < nl; ++s) {
+      const int l = adjoint ? nl - 1 - s : s;
+      push(bi.lvl_begin[l], bi.lvl_end[l], s == nl - 1 ? 1 : 0, 0);
+    }
+  }
+  sweep_rec(P, level_base, dd + 1, second, lower_dir, adjoint, leaf_units, out);
+}
+
+void build_sweeps(const Plan& P, Sweeps& S) {
+  std::vector<int> level_base(P.V + 1, 0);
+  {
+    int cur = 0;
+    for (int v = 1; v < P.V; ++v) {
+      level_base[v] = cur;
+      cur += 2 * (1 << (v - 1));
+    }
+  }
+  S.fwd.clear();
+  S.bwd.clear();
+  S.adj_fwd.clear();
+  S.adj_bwd.clear();
+  if (P.leaf_fwd_unit.empty()) return;
+  // P^{-1}: lower sweep with the forward leaf solves, upper with the backward ones
+  sweep_rec(P, level_base, 0, 0, true, false, P.leaf_fwd_unit, S.fwd);
+  sweep_rec(P, level_base, 0, 0, false, false, P.leaf_bwd_unit, S.bwd);
+  // P^{-H}: the lower sweep solves with the backward leaf matrices conjugate-
+  // transposed, the upper sweep with the forward ones
+  sweep_rec(P, level_base, 0, 0, true, true, P.leaf_bwd_unit, S.adj_fwd);
+  sweep_rec(P, level_base, 0, 0, false, true, P.leaf_fwd_unit, S.adj_bwd);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 host executor of a schedule (the same unit semantics as the device
+// stage kernel).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Seg {
+  cplx* base;
+  int64_t off;
+  int len;
+};
+
+void unit_eval(const Plan& P, const Unit& u, bool adj, const std::vector<cplx>& src, std::vector<cplx>& dst) {
+  const cplx* M = P.fac.data() + u.mat;
+  const uint8_t* pm = P.perm.data() + u.perm;
+  const int nin = u.in_len[0] + u.in_len[1];
+  const int nout = u.out_len[0] + u.out_len[1];
+  if (u.type == UNIT_DENSE) {
+    if (!adj) {
+      for (int i = 0; i < nout; ++i) {
+        cplx a = 0;
+        for (int t = 0; t < nin; ++t) a += M[static_cast<size_t>(t) * nout + i] * src[t];
+        dst[i] += a;
+      }
+    } else {
+      for (int t = 0; t < nin; ++t) {
+        cplx a = 0;
+        for (int i = 0; i < nout; ++i) a += std::conj(M[static_cast<size_t>(t) * nout + i]) * src[i];
+        dst[t] += a;
+      }
+    }
+    return;
+  }
+  if (u.type == UNIT_GATHER) {
+    // forward: src = in_cat (nin), dst = [out_a; out_b]
+    int mo = 0, po = 0, base = 0;
+    for (int o = 0; o < 2; ++o) {
+      const int k = u.k[o];
+      const int r = nin - k;
+      const cplx* T = M + mo;
+      const uint8_t* perm = pm + po;
+      if (!adj) {
+        for (int i = 0; i < k; ++i) {
+          cplx a = src[perm[i]];
+          for (int t = 0; t < r; ++t) a += T[static_cast<size_t>(t) * k + i] * src[perm[k + t]];
+          dst[base + i] += a;
+        }
+      } else {
+        // src = [out_a; out_b], dst = in_cat
+        for (int i = 0; i < k; ++i) dst[perm[i]] += src[base + i];
+        for (int t = 0; t < r; ++t) {
+          cplx a = 0;
+          for (int i = 0; i < k; ++i) a += std::conj(T[static_cast<size_t>(t) * k + i]) * src[base + i];
+          dst[perm[k + t]] += a;
+        }
+      }
+      mo += k * r;
+      po += nin;
+      base += k;
+    }
+    return;
+  }
+  // SCATTER: forward src = [in_a; in_b], dst = out_cat (nout)
+  int mo = 0, po = 0, base = 0;
+  for (int o = 0; o < 2; ++o) {
+    const int k = u.k[o];
+    const int r = nout - k;
+    const cplx* T = M + mo;          // row-major k x r
+    const uint8_t* inv = pm + po;    // invperm over nout
+    if (!adj) {
+      for (int p = 0; p < nout; ++p) {
+        const int q = inv[p];
+        cplx a;
+        if (q < k) {
+          a = src[base + q];
+        } else {
+          a = 0;
+          for (int j = 0; j < k; ++j) a += T[static_cast<size_t>(j) * r + (q - k)] * src[base + j];
+        }
+        dst[p] += a;
+      }
+    } else {
+      // src = out_cat, dst = [in_a; in_b]
+      for (int p = 0; p < nout; ++p) {
+        const int q = inv[p];
+        if (q < k) {
+          dst[base + q] += src[p];
+        } else {
+          for (int j = 0; j < k; ++j) dst[base + j] += std::conj(T[static_cast<size_t>(j) * r + (q - k)]) * src[p];
+        }
+      }
+    }
+    mo += k * r;
+    po += nout;
+    base += k;
+  }
+}
+
+}  // namespace
+
+void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
+               cplx* arena, int R, cplx alpha) {
+  auto bufp = [&](uint8_t id) -> cplx* { return id == BUF_X ? X : id == BUF_Y ? Y : arena; };
+  std::vector<cplx> src, dst;
+  for (const Launch& L : launches) {
+    for (int g = L.first; g < L.first + L.count; ++g) {
+      std::vector<int32_t> us;
+      if (L.direct) {
+        us.push_back(g);
+      } else {
+        for (int32_t q = P.group_off[g]; q < P.group_off[g + 1]; ++q) us.push_back(P.group_units[q]);
+      }
+      // destination segments are those of the first unit (shared by the group)
+      const Unit& u0 = P.units[us[0]];
+      const uint8_t dbuf = adj ? u0.in_buf : u0.out_buf;
+      const int32_t* doff = adj ? u0.in_off : u0.out_off;
+      const int16_t* dlen = adj ? u0.in_len : u0.out_len;
+      const int nd = dlen[0] + dlen[1];
+      for (int r = 0; r < R; ++r) {
+        dst.assign(nd, cplx(0.0));
+        for (int32_t uid : us) {
+          const Unit& u = P.units[uid];
+          const uint8_t sbuf = adj ? u.out_buf : u.in_buf;
+          const int32_t* soff = adj ? u.out_off : u.in_off;
+          const int16_t* slen = adj ? u.out_len : u.in_len;
+          const int ns = slen[0] + slen[1];
+          src.resize(ns);
+          cplx* sb = bufp(sbuf);
+          for (int t = 0; t < slen[0]; ++t) src[t] = sb[(static_cast<int64_t>(soff[0]) + t) * R + r];
+          for (int t = 0; t < slen[1]; ++t) src[slen[0] + t] = sb[(static_cast<int64_t>(soff[1]) + t) * R + r];
+          unit_eval(P, u, adj, src, dst);
+        }
+        cplx* db = bufp(dbuf);
+        int pos = 0;
+        for (int s = 0; s < 2; ++s) {
+          for (int t = 0; t < dlen[s]; ++t, ++pos) {
+            cplx& o = db[(static_cast<int64_t>(doff[s]) + t) * R + r];
+            o = L.out_leaf ? o + alpha * dst[pos] : dst[pos];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Leaf factorisation on the host in FP64 (construction checks only): writes
+// the leaf-solve matrices into the leaf region of P.fac.
+static void invert_dense(std::vector<cplx>& A, int n) {
+  // Gauss-Jordan with partial pivoting on a row-major n x n matrix
+  std::vector<cplx> I(static_cast<size_t>(n) * n, cplx(0.0));
+  for (int i = 0; i < n; ++i) I[static_cast<size_t>(i) * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    double best = std::abs(A[static_cast<size_t>(c) * n + c]);
+    for (int r = c + 1; r < n; ++r) {
+      const double v = std::abs(A[static_cast<size_t>(r) * n + c]);
+      if (v > best) { best = v; p = r; }
+    }
+    if (best == 0.0) throw std::runtime_error("singular leaf block");
+    if (p != c) {
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[static_cast<size_t>(p) * n + j], A[static_cast<size_t>(c) * n + j]);
+        std::swap(I[static_cast<size_t>(p) * n + j], I[static_cast<size_t>(c) * n + j]);
+      }
+    }
+    const cplx inv = 1.0 / A[static_cast<size_t>(c) * n + c];
+    for (int j = 0; j < n; ++j) {
+      A[static_cast<size_t>(c) * n + j] *= inv;
+      I[static_cast<size_t>(c) * n + j] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const cplx f = A[static_cast<size_t>(r) * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        A[static_cast<size_t>(r) * n + j] -= f * A[static_cast<size_t>(c) * n + j];
+        I[static_cast<size_t>(r) * n + j] -= f * I[static_cast<size_t>(c) * n + j];
+      }
+    }
+  }
+  A.swap(I);
+}
+
+void host_leaf_factor(Plan& P, hbf_prec prec) {
+  if (P.leaf_fwd_unit.empty()) return;
+  P.fac.resize(P.leaf_fac_begin + P.leaf_fac_len, cplx(0.0));
+  const int n0 = P.n0;
+  const int64_t nl = P.n / n0;
+  for (int64_t b = 0; b < nl; ++b) {
+    const Unit& du = P.units[P.diag_unit[b]];
+    std::vector<cplx> A(static_cast<size_t>(n0) * n0);  // row-major copy of A_bb
+    for (int t = 0; t < n0; ++t)
+      for (int i = 0; i < n0; ++i) A[static_cast<size_t>(i) * n0 + t] = P.fac[du.mat + static_cast<size_t>(t) * n0 + i];
+    auto store = [&](const std::vector<cplx>& Minv, const Unit& u) {
+      for (int t = 0; t < n0; ++t)
+        for (int i = 0; i < n0; ++i) P.fac[u.mat + static_cast<size_t>(t) * n0 + i] = Minv[static_cast<size_t>(i) * n0 + t];
+    };
+    if (prec == HBF_PREC_BLOCK_LU) {
+      invert_dense(A, n0);
+      store(A, P.units[P.leaf_fwd_unit[b]]);
+    } else {
+      std::vector<cplx> Lm(static_cast<size_t>(n0) * n0, cplx(0.0)), Um(static_cast<size_t>(n0) * n0, cplx(0.0));
+      for (int i = 0; i < n0; ++i)
+        for (int j = 0; j < n0; ++j) {
+          const cplx a = A[static_cast<size_t>(i) * n0 + j];
+          if (i > j) Lm[static_cast<size_t>(i) * n0 + j] = P.scale * a;
+          if (i == j) Lm[static_cast<size_t>(i) * n0 + j] = 1.0;
+          if (i <= j) Um[static_cast<size_t>(i) * n0 + j] = a;
+        }
+      invert_dense(Lm, n0);
+      invert_dense(Um, n0);
+      store(Lm, P.units[P.leaf_fwd_unit[b]]);
+      store(Um, P.units[P.leaf_bwd_unit[b]]);
+    }
+  }
+}
+
+}  // namespace hbf
+
+// ---------------------------------------------------------------------------
+// host-only C ABI
+// ---------------------------------------------------------------------------
+using namespace hbf;
+
+struct hbf_plan {
+  Plan P;
+  Sweeps S;
+  hbf_prec prec = HBF_PREC_BLOCK_LU;
+};
+
+extern "C" {
+
+const char* hbf_last_error(void) { return hbf::last_error(); }
+
+void hbf_hankel2_0(const double* x, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const cplx h = hankel2_0(x[i]);
+    out[2 * i] = h.real();
+    out[2 * i + 1] = h.imag();
+  }
+}
+
+hbf_status hbf_plan_build(const hbf_curve* curve, double kappa, int32_t leaf, double tol,
+                          const hbf_build_opts* opts, hbf_plan** out) {
+  if (!out) { set_error("hbf_plan_build: out is NULL"); return HBF_EINVAL; }
+  *out = nullptr;
+  try {
+    auto p = std::make_unique<hbf_plan>();
+    build_plan(p->P, curve, kappa, leaf, tol, opts);
+    p->prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
+    host_leaf_factor(p->P, p->prec);
+    build_sweeps(p->P, p->S);
+    *out = p.release();
+    return HBF_OK;
+  } catch (const std::invalid_argument& e) {
+    set_error(e.what());
+    return HBF_EINVAL;
+  } catch (const std::bad_alloc&) {
+    set_error("hbf_plan_build: out of host memory");
+    return HBF_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return HBF_ESINGULAR;
+  }
+}
+
+hbf_status hbf_plan_apply(const hbf_plan* plan, const double* x, double* y, int32_t nrhs, int32_t adjoint) {
+  if (!plan || !x || !y || nrhs < 1) { set_error("hbf_plan_apply: bad arguments"); return HBF_EINVAL; }
+  const Plan& P = plan->P;
+  const int64_t N = P.n;
+  // internal layout (N, R)
+  std::vector<cplx> xi(N * nrhs), yi(N * nrhs), arena(P.arena_rows * nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int64_t i = 0; i < N; ++i) xi[i * nrhs + r] = cplx(x[2 * (r * N + i)], x[2 * (r * N + i) + 1]);
+  if (!adjoint) exec_host(P, P.mv_fwd, false, xi.data(), yi.data(), arena.data(), nrhs, 0.0);
+  else exec_host(P, P.mv_adj, true, yi.data(), xi.data(), arena.data(), nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r)
+    for (int64_t i = 0; i < N; ++i) {
+      y[2 * (r * N + i)] = yi[i * nrhs + r].real();
+      y[2 * (r * N + i) + 1] = yi[i * nrhs + r].imag();
+    }
+  return HBF_OK;
+}
+
+hbf_status hbf_plan_precond(const hbf_plan* plan, const double* rin, double* zout, int32_t nrhs, int32_t adjoint) {
+  if (!plan || !rin || !zout || nrhs < 1) { set_error("hbf_plan_precond: bad arguments"); return HBF_EINVAL; }
+  const Plan& P = plan->P;
+  const Sweeps& S = plan->S;
+  const int64_t N = P.n;
+  std::vector<cplx> u(N * nrhs), t(N * nrhs), z(N * nrhs), arena(P.arena_rows * nrhs);
+  for (int r = 0; r < nrhs; ++r)
+    for (int64_t i = 0; i < N; ++i) u[i * nrhs + r] = cplx(rin[2 * (r * N + i)], rin[2 * (r * N + i) + 1]);
+  if (plan->prec == HBF_PREC_NONE) {
+    z = u;
+  } else {
+    const bool paper = plan->prec == HBF_PREC_PAPER_TRI;
+    const cplx a = paper ? P.scale : cplx(1.0);
+    if (!adjoint) {
+      exec_host(P, S.fwd, false, t.data(), u.data(), arena.data(), nrhs, -a);
+      cplx* mid = paper ? t.data() : u.data();
+      exec_host(P, S.bwd, false, z.data(), mid, arena.data(), nrhs, -1.0);
+    } else {
+      exec_host(P, S.adj_fwd, true, u.data(), t.data(), arena.data(), nrhs, -1.0);
+      cplx* mid = paper ? t.data() : u.data();
+      exec_host(P, S.adj_bwd, true, mid, z.data(), arena.data(), nrhs, -std::conj(a));
+    }
+  }
+  for (int r = 0; r < nrhs; ++r)
+    for (int64_t i = 0; i < N; ++i) {
+      zout[2 * (r * N + i)] = z[i * nrhs + r].real();
+      zout[2 * (r * N + i) + 1] = z[i * nrhs + r].imag();
+    }
+  return HBF_OK;
+}
+
+hbf_status hbf_plan_entries(const hbf_plan* plan, const int64_t* rows, int64_t nr, const int64_t* cols,
+                            int64_t nc, double* out) {
+  if (!plan || !rows || !cols || !out) { set_error("hbf_plan_entries: bad arguments"); return HBF_EINVAL; }
+  for (int64_t a = 0; a < nr; ++a)
+    for (int64_t b = 0; b < nc; ++b) {
+      if (rows[a] < 0 || rows[a] >= plan->P.n || cols[b] < 0 || cols[b] >= plan->P.n) {
+        set_error("hbf_plan_entries: index out of range");
+        return HBF_EINVAL;
+      }
+      const cplx e = plan->P.entry(rows[a], cols[b]);
+      out[2 * (a * nc + b)] = e.real();
+      out[2 * (a * nc + b) + 1] = e.imag();
+    }
+  return HBF_OK;
+}
+
+void fill_stats(const Plan& P, hbf_stats_t* s, int elt) {
+  std::memset(s, 0, sizeof(*s));
+  s->n = P.n;
+  s->leaf = P.n0;
+  s->levels = P.V;
+  s->n_blocks = static_cast<int64_t>(P.blocks.size());
+  s->n_units = static_cast<int64_t>(P.units.size());
+  s->max_rank = P.max_rank;
+  s->mean_rank = P.n_ids ? P.sum_rank / P.n_ids : 0.0;
+  s->bytes_butterfly = P.bytes_butterfly_c128 / 16 * elt;
+  s->bytes_dense = P.bytes_dense_c128 / 16 * elt;
+  s->bytes_precond = P.leaf_fac_len * elt;
+  s->build_seconds = P.build_seconds;
+  s->scale_re = P.scale.real();
+  s->scale_im = P.scale.imag();
+}
+
+hbf_status hbf_plan_stats(const hbf_plan* plan, hbf_stats_t* out) {
+  if (!plan || !out) { set_error("hbf_plan_stats: bad arguments"); return HBF_EINVAL; }
+  fill_stats(plan->P, out, 16);
+  out->bytes_index = static_cast<int64_t>(plan->P.perm.size());
+  return HBF_OK;
+}
+
+void hbf_plan_free(hbf_plan* plan) { delete plan; }
+
+}  // extern "C"

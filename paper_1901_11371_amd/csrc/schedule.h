@@ -1,0 +1,31 @@
+// Sweep schedules and the host executor (shared by the host checks and the
+// device context, which uploads the same launch lists).
+#pragma once
+
+#include <vector>
+
+#include "hbf_internal.h"
+
+namespace hbf {
+
+struct Sweeps {
+  std::vector<Launch> fwd, bwd;          // P^{-1}: lower then upper substitution
+  std::vector<Launch> adj_fwd, adj_bwd;  // P^{-H}
+};
+
+void build_sweeps(const Plan& P, Sweeps& S);
+
+// Run a schedule on host buffers in the internal (rows, R) layout.  In
+// adjoint mode every unit reads its forward output segments and writes its
+// forward input segments.  Launches with out_leaf set add alpha * result to
+// the destination; the others overwrite it.
+void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
+               cplx* arena, int R, cplx alpha);
+
+void host_leaf_factor(Plan& P, hbf_prec prec);
+
+const char* last_error();
+
+}  // namespace hbf
+
+extern "C" void fill_stats(const hbf::Plan& P, hbf_stats_t* s, int elt);

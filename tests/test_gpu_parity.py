@@ -1,0 +1,144 @@
+"""GPU parity of the HIP hot path against the CPU FP64 oracle, through the
+C ABI: matvec (forward and adjoint), the approximate-LU preconditioner in
+both readings (forward and adjoint), complex64 and complex128 storage,
+batched vs single right-hand sides, and argument checks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import efie
+from paper_1901_11371_amd import inputs
+
+pytestmark = pytest.mark.gpu
+KAPPA = 2 * math.pi
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def spiral(torch):
+    c = inputs.archimedean_spiral(4096)
+    rho, w = efie.segments(c.xy, c.node_off)
+    return c, efie.dense_A(rho, w, KAPPA)
+
+
+@pytest.fixture(scope="module")
+def strip(torch):
+    wl = inputs.workload(0)
+    rho, w = efie.segments(wl.curves.xy, wl.curves.node_off)
+    return wl.curves, efie.dense_A(rho, w, KAPPA)
+
+
+def _ctx(c, dtype, prec="block", max_nrhs=8, z=None):
+    from paper_1901_11371_amd.hbf import Context
+    return Context(c, KAPPA, 64, 1e-6, dtype=dtype, prec=prec, max_nrhs=max_nrhs, z=z)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", ["strip", "spiral"])
+def test_matvec_matches_oracle(torch, strip, spiral, dtype, case):
+    c, A = strip if case == "strip" else spiral
+    _say(f"[matvec] case={case} dtype={dtype} N=4096")
+    ctx = _ctx(c, dtype)
+    x = inputs.random_complex(4096, 31)
+    td = torch.complex64 if dtype == "c64" else torch.complex128
+    y = ctx.matvec(torch.tensor(x, dtype=td, device="cuda")).cpu().numpy()
+    torch.cuda.synchronize()
+    err = _rel(y, A @ x)
+    _say(f"  rel err {err:.3e}")
+    assert err < 5e-6
+    ya = ctx.matvec(torch.tensor(x, dtype=td, device="cuda"), adjoint=True).cpu().numpy()
+    erra = _rel(ya, A.conj().T @ x)
+    _say(f"  adjoint rel err {erra:.3e}")
+    assert erra < 5e-6
+    ctx.close()
+
+
+def test_matvec_batched_equals_single_and_fp64_io(torch, spiral):
+    c, A = spiral
+    _say("[matvec batched] spiral c64 R=5")
+    ctx = _ctx(c, "c64")
+    X = inputs.random_complex((5, 4096), 32)
+    Xt = torch.tensor(X, dtype=torch.complex64, device="cuda")
+    Y = ctx.matvec(Xt).cpu().numpy()
+    for r in range(5):
+        y1 = ctx.matvec(Xt[r].contiguous()).cpu().numpy()
+        assert _rel(Y[r], y1) < 1e-6
+    assert _rel(Y, X @ A.T) < 5e-6
+    # complex128 io on the complex64 context: FP64 accumulation
+    Y64 = ctx.matvec(torch.tensor(X, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    e64 = _rel(Y64, X @ A.T)
+    _say(f"  c128-io rel err {e64:.3e}")
+    assert e64 < 5e-6
+    for adj in (False, True):
+        Ya = ctx.matvec(Xt, adjoint=adj).cpu().numpy()
+        ref = X @ (A.conj() if adj else A.T)
+        assert _rel(Ya, ref) < 5e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["block", "paper"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_precond_matches_oracle(torch, spiral, prec, dtype):
+    c, A = spiral
+    _say(f"[precond] prec={prec} dtype={dtype}")
+    ctx = _ctx(c, dtype, prec=prec)
+    td = torch.complex64 if dtype == "c64" else torch.complex128
+    R = inputs.random_complex((3, 4096), 33)
+    f = (lambda v, adj: efie.precond_block_apply(A, v, 64, adjoint=adj)) if prec == "block" else \
+        (lambda v, adj: efie.precond_paper_apply(A, v, adjoint=adj))
+    for adj in (False, True):
+        Z = ctx.precond(torch.tensor(R, dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
+        ref = np.stack([f(R[i], adj) for i in range(3)])
+        err = _rel(Z, ref)
+        _say(f"  adjoint={adj} rel err {err:.3e}")
+        assert err < (2e-6 if dtype == "c128" else 5e-5)
+        z1 = ctx.precond(torch.tensor(R[1], dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
+        assert _rel(z1, Z[1]) < (1e-12 if dtype == "c128" else 1e-5)
+    ctx.close()
+
+
+def test_nrhs_beyond_max_is_rejected(torch, spiral):
+    from paper_1901_11371_amd._capi import HBF_EINVAL, HbfError
+    c, _ = spiral
+    ctx = _ctx(c, "c64", max_nrhs=2)
+    x = torch.zeros((3, 4096), dtype=torch.complex64, device="cuda")
+    with pytest.raises(HbfError) as e:
+        ctx.matvec(x)
+    assert e.value.status == HBF_EINVAL
+    with pytest.raises(HbfError):
+        ctx.precond(torch.zeros((4096,), dtype=torch.complex128, device="cuda"))
+    ctx.close()
+
+
+def test_impedance_and_refactor(torch):
+    _say("[impedance] semicircle 2048")
+    c = inputs.semicircle(2048)
+    rho, w = efie.segments(c.xy, c.node_off)
+    z = inputs.impedance(2048, 7)
+    ctx = _ctx(c, "c128")
+    ctx.set_impedance(z)
+    A = efie.dense_A(rho, w, KAPPA, z=z)
+    x = inputs.random_complex(2048, 34)
+    y = ctx.matvec(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert _rel(y, A @ x) < 5e-6
+    zz = ctx.precond(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert _rel(zz, efie.precond_block_apply(A, x, 64)) < 2e-6
+    ctx.close()

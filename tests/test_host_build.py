@@ -1,0 +1,151 @@
+"""CPU checks of the native library: it loads and exports every entry point
+of include/hbf.h, its own Hankel and entry evaluation agree with the oracle,
+and the host-side H-IDBF factorisation (evaluated in FP64 on the host by the
+library's construction-check entry points) reproduces the dense oracle's
+operator and preconditioner."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import efie
+from paper_1901_11371_amd import _capi, inputs
+from paper_1901_11371_amd.hbf import HostPlan, hankel2_0
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KAPPA = 2 * math.pi
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = _capi.load()
+    hdr = open(os.path.join(ROOT, "include", "hbf.h")).read()
+    names = set(re.findall(r"\b(hbf_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) >= 15
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def test_library_hankel_matches_oracle():
+    xs = np.concatenate([np.logspace(-3, 6, 400), np.linspace(0.5, 40, 400)])
+    h = hankel2_0(xs)
+    ref = efie.hankel2_0(xs)
+    assert np.max(np.abs(h - ref) / np.abs(ref)) < 5e-14
+
+
+def _plan(curves, tol=1e-6, prec="block", z=None):
+    return HostPlan(curves, KAPPA, 64, tol, prec=prec, z=z)
+
+
+def test_library_entries_match_oracle():
+    c = inputs.archimedean_spiral(512)
+    z = inputs.impedance(512, 3)
+    p = _plan(c, z=z)
+    rho, w = efie.segments(c.xy, c.node_off)
+    rows = np.array([0, 5, 100, 511])
+    cols = np.arange(0, 512, 7)
+    got = p.entries(rows, cols)
+    ref = efie.entries(rows, cols, rho, w, KAPPA, z=z)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-13
+
+
+@pytest.fixture(scope="module")
+def spiral4096():
+    c = inputs.archimedean_spiral(4096)
+    rho, w = efie.segments(c.xy, c.node_off)
+    return c, efie.dense_A(rho, w, KAPPA)
+
+
+@pytest.fixture(scope="module")
+def strip4096():
+    w = inputs.workload(0)
+    rho, ww = efie.segments(w.curves.xy, w.curves.node_off)
+    return w.curves, efie.dense_A(rho, ww, KAPPA)
+
+
+@pytest.mark.parametrize("case", ["strip", "spiral"])
+def test_host_plan_matvec_matches_dense(case, strip4096, spiral4096):
+    c, A = strip4096 if case == "strip" else spiral4096
+    p = _plan(c)
+    x = inputs.random_complex((3, 4096), 21)
+    y = p.apply(x)
+    ref = x @ A.T
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err < 1e-6, err
+    ya = p.apply(x, adjoint=True)
+    refa = x @ A.conj()
+    assert np.linalg.norm(ya - refa) / np.linalg.norm(refa) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["block", "paper"])
+def test_host_plan_preconditioner_matches_dense(prec, spiral4096):
+    c, A = spiral4096
+    p = _plan(c, prec=prec)
+    r = inputs.random_complex(4096, 22)
+    f = (lambda v, adj=False: efie.precond_block_apply(A, v, 64, adjoint=adj)) if prec == "block" else \
+        (lambda v, adj=False: efie.precond_paper_apply(A, v, adjoint=adj))
+    for adj in (False, True):
+        z = p.precond(r, adjoint=adj)
+        ref = f(r, adj)
+        assert np.linalg.norm(z - ref) / np.linalg.norm(ref) < 2e-6, (prec, adj)
+
+
+def test_host_plan_tight_tolerance_is_exact(spiral4096):
+    """tol -> 0: every ID keeps (numerically) its full rank and the compressed
+    operator reproduces the dense one to near machine precision."""
+    c, A = spiral4096
+    p = _plan(c, tol=1e-13)
+    x = inputs.random_complex(4096, 23)
+    assert np.linalg.norm(p.apply(x) - A @ x) / np.linalg.norm(A @ x) < 1e-10
+
+
+def test_host_plan_with_impedance():
+    c = inputs.semicircle(2048)
+    z = inputs.impedance(2048, 5)
+    rho, w = efie.segments(c.xy, c.node_off)
+    A = efie.dense_A(rho, w, KAPPA, z=z)
+    p = _plan(c, z=z)
+    x = inputs.random_complex(2048, 24)
+    assert np.linalg.norm(p.apply(x) - A @ x) / np.linalg.norm(A @ x) < 1e-6
+    r = inputs.random_complex(2048, 25)
+    ref = efie.precond_block_apply(A, r, 64)
+    assert np.linalg.norm(p.precond(r) - ref) / np.linalg.norm(ref) < 2e-6
+
+
+def test_host_plan_multi_curve():
+    c = inputs.multi_curve(4096)
+    rho, w = efie.segments(c.xy, c.node_off)
+    A = efie.dense_A(rho, w, KAPPA)
+    p = _plan(c)
+    x = inputs.random_complex(4096, 26)
+    assert np.linalg.norm(p.apply(x) - A @ x) / np.linalg.norm(A @ x) < 1e-6
+
+
+def test_smallest_hierarchy():
+    """N = 2 n0: a single pair of dense neighbour blocks, no butterfly block."""
+    c = inputs.strip(128)
+    rho, w = efie.segments(c.xy, c.node_off)
+    A = efie.dense_A(rho, w, KAPPA)
+    p = _plan(c)
+    x = inputs.random_complex(128, 27)
+    assert np.linalg.norm(p.apply(x) - A @ x) / np.linalg.norm(A @ x) < 1e-13
+    assert p.stats["n_blocks"] == 0
+
+
+@pytest.mark.parametrize("n,leaf,tol", [(4000, 64, 1e-6), (64, 64, 1e-6), (4096, 1, 1e-6), (4096, 64, 0.0),
+                                        (4096, 64, 1.5)])
+def test_invalid_arguments_rejected(n, leaf, tol):
+    c = inputs.strip(n)
+    with pytest.raises(_capi.HbfError) as e:
+        HostPlan(c, KAPPA, leaf, tol)
+    assert e.value.status == _capi.HBF_EINVAL
+
+
+def test_rank_statistics_and_storage():
+    c = inputs.archimedean_spiral(8192)
+    p = _plan(c)
+    st = p.stats
+    assert 4 < st["mean_rank"] < 40 and st["max_rank"] <= 127
+    # compressed storage well below the dense N^2 entries
+    assert st["bytes_butterfly"] + st["bytes_dense"] < 0.3 * 16 * 8192 ** 2
