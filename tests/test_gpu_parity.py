@@ -123,8 +123,9 @@ def test_nrhs_beyond_max_is_rejected(torch, spiral):
     with pytest.raises(HbfError) as e:
         ctx.matvec(x)
     assert e.value.status == HBF_EINVAL
-    with pytest.raises(HbfError):
-        ctx.precond(torch.zeros((4096,), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(HbfError) as e:
+        ctx.precond(x)
+    assert e.value.status == HBF_EINVAL
     ctx.close()
 
 
