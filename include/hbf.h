@@ -80,6 +80,9 @@ typedef struct {
   int32_t restart;   /* GMRES restart length used to size the Krylov workspace; <= 0 selects 30 */
   int32_t device;    /* HIP device ordinal */
   int32_t nthreads;  /* host threads for the construction; <= 0 = all hardware threads */
+  int32_t cache_plan; /* 1: keep this host factorisation in a one-entry process cache, so a later
+                         build of the same curve/kappa/leaf/tol/preconditioner (any dtype) skips
+                         the host construction; 0: no caching (a cache hit is still used) */
 } hbf_build_opts;
 
 typedef struct {

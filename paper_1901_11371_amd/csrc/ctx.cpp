@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -45,6 +46,7 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_units);
   dfree(c->d_gofs);
   dfree(c->d_gunits);
+  dfree(c->d_steps);
   dfree(c->d_arena);
   dfree(c->d_vin);
   dfree(c->d_vout);
@@ -134,6 +136,42 @@ void factor_leaves(hbf_ctx* c, hipStream_t s) {
   }
 }
 
+// One-entry process cache of a host factorisation (factor entries included),
+// keyed by everything the construction depends on.
+struct PlanCache {
+  std::mutex mu;
+  bool valid = false;
+  uint64_t key = 0;
+  Plan plan;
+};
+PlanCache& plan_cache() {
+  static PlanCache c;
+  return c;
+}
+
+uint64_t plan_key(const hbf_curve* curve, double kappa, int leaf, double tol, const hbf_build_opts* opts) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+  };
+  mix(&curve->ncurves, sizeof(curve->ncurves));
+  mix(curve->node_off, sizeof(int64_t) * (curve->ncurves + 1));
+  mix(curve->xy, sizeof(double) * 2 * curve->node_off[curve->ncurves]);
+  mix(&kappa, sizeof(kappa));
+  mix(&leaf, sizeof(leaf));
+  mix(&tol, sizeof(tol));
+  const int prec = opts ? opts->prec : 0;
+  mix(&prec, sizeof(prec));
+  const double eta0 = opts ? opts->eta0 : 0.0;
+  mix(&eta0, sizeof(eta0));
+  if (opts && opts->z) {
+    const int64_t n = curve->node_off[curve->ncurves] - curve->ncurves;
+    mix(opts->z, sizeof(double) * 2 * n);
+  }
+  return h;
+}
+
 hbf_status fail(hbf_status st, const std::string& msg) {
   set_error(msg);
   return st;
@@ -149,6 +187,41 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
   const size_t szF = c->elt;
   const int ch_cap = static_cast<int>(32768 / szF);
   for (const Launch& l : L) {
+    if (l.prog) {
+      // one workgroup per RHS chunk; each wave owns an LDS slice
+      StageArgs a;
+      a.units = c->d_units;
+      a.gofs = c->d_gofs;
+      a.gunits = c->d_gunits;
+      a.fac = c->d_fac;
+      a.perm = c->d_perm;
+      a.buf[BUF_X] = X;
+      a.buf[BUF_Y] = Y;
+      a.buf[BUF_ARENA] = c->d_arena;
+      a.first = 0;
+      a.direct = 1;
+      a.R = R;
+      const int md = std::max(1, l.max_dst);
+      int rc = std::min(R, std::max(1, (64 * kProgOutPerThread) / md));
+      const int wave_lds = 8192;
+      while (rc > 1 && static_cast<size_t>(l.max_src) * rc * szA > 2048) --rc;
+      a.rc = rc;
+      a.nchunks = (R + rc - 1) / rc;
+      a.acc = 0;
+      a.alpha_re = alpha_re;
+      a.alpha_im = alpha_im;
+      a.src_cap = std::max(1, l.max_src * rc);
+      int ch = static_cast<int>((wave_lds - 1024 - static_cast<size_t>(a.src_cap) * szA) / szF);
+      ch &= ~1;
+      ch = std::min(ch, (l.max_mat + 1) & ~1);
+      if (ch < 2) ch = 2;
+      a.ch = ch;
+      hipError_t e = (c->dtype == HBF_C128)
+                         ? launch_program_c128(a, c->d_steps, l.first, l.first + l.count, wave_lds, adjoint, s)
+                         : launch_program_c64(a, c->d_steps, l.first, l.first + l.count, wave_lds, adjoint, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     StageArgs a;
     a.units = c->d_units;
     a.gofs = c->d_gofs;
@@ -162,6 +235,27 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     a.direct = l.direct;
     a.R = R;
     const int md = std::max(1, l.max_dst);
+    if (c->wave_units && md * std::min(R, 2) <= 64 * kWaveOutPerThread && R <= 2) {
+      // small groups: one wave per group
+      a.rc = R;
+      a.nchunks = 1;
+      a.acc = l.out_leaf;
+      a.alpha_re = alpha_re;
+      a.alpha_im = alpha_im;
+      a.src_cap = std::max(1, l.max_src * R);
+      const int wave_lds = 8192;
+      int ch = static_cast<int>((wave_lds - 1024 - static_cast<size_t>(a.src_cap) * szA) / szF);
+      ch &= ~1;
+      ch = std::min(ch, (l.max_mat + 1) & ~1);
+      if (ch < 2) ch = 2;
+      a.ch = ch;
+      hipError_t e;
+      if (c->dtype == HBF_C128) e = launch_stage_wave_c128(a, l.count, wave_lds, adjoint, s);
+      else if (vec_c128) e = launch_stage_wave_c64_hi(a, l.count, wave_lds, adjoint, s);
+      else e = launch_stage_wave_c64(a, l.count, wave_lds, adjoint, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     int rc = std::min(R, std::max(1, (kStageThreads * kOutPerThread) / md));
     while (rc > 1 && static_cast<size_t>(l.max_src) * rc * szA > 24576) --rc;
     a.rc = rc;
@@ -252,7 +346,29 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     hip_check(hipSetDevice(c->device), "hipSetDevice");
     hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
 
-    build_plan(c->P, curve, kappa, leaf, tol, opts);
+    if (!curve || curve->ncurves < 1 || !curve->node_off || !curve->xy)
+      return fail(HBF_EINVAL, "hbf_build: empty curve");
+    {
+      const uint64_t key = plan_key(curve, kappa, leaf, tol, opts);
+      PlanCache& pc = plan_cache();
+      bool hit = false;
+      {
+        std::lock_guard<std::mutex> lk(pc.mu);
+        if (pc.valid && pc.key == key) {
+          c->P = pc.plan;
+          hit = true;
+        }
+      }
+      if (!hit) {
+        build_plan(c->P, curve, kappa, leaf, tol, opts);
+        if (opts && opts->cache_plan) {
+          std::lock_guard<std::mutex> lk(pc.mu);
+          pc.plan = c->P;
+          pc.key = key;
+          pc.valid = true;
+        }
+      }
+    }
     build_sweeps(c->P, c->S);
     Plan& P = c->P;
     c->n = P.n;
@@ -290,6 +406,10 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     hip_check(hipMemcpy(c->d_gunits, P.group_units.data(), P.group_units.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice),
               "groups");
+    dmalloc(&c->d_steps, std::max<size_t>(c->S.steps.size(), 1) * sizeof(int32_t), "steps");
+    if (!c->S.steps.empty())
+      hip_check(hipMemcpy(c->d_steps, c->S.steps.data(), c->S.steps.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                "steps");
     const size_t R = static_cast<size_t>(c->max_nrhs);
     const size_t vbytes = static_cast<size_t>(N) * R * 16;
     dmalloc(&c->d_arena, static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16, "arena");

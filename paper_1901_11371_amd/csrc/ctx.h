@@ -19,6 +19,7 @@ struct hbf_ctx {
   int restart = 30;
   int64_t n = 0;
   int elt = 8;                 // bytes per factor entry
+  bool wave_units = true;      // one wave per group for one- or two-RHS launches
 
   // device memory
   void* d_fac = nullptr;       // factors + leaf inverses (storage dtype)
@@ -26,6 +27,7 @@ struct hbf_ctx {
   hbf::Unit* d_units = nullptr;
   int32_t* d_gofs = nullptr;
   int32_t* d_gunits = nullptr;
+  int32_t* d_steps = nullptr;  // program steps of the sweeps
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
   void* d_vin = nullptr;       // internal-layout vectors, N x max_nrhs x 16 bytes each
   void* d_vout = nullptr;

@@ -64,13 +64,14 @@ static_assert(sizeof(Unit) == 64, "Unit must be 64 bytes");
 // the single unit unit_begin + g).
 struct Launch {
   int32_t direct;
-  int32_t first;       // first group (or first unit when direct)
-  int32_t count;       // number of groups
+  int32_t first;       // first group (or first unit when direct; first step of a program)
+  int32_t count;       // number of groups (number of steps of a program)
   int32_t max_src;     // largest source length of any unit in the launch
   int32_t max_dst;
   int32_t max_mat;     // largest matrix (complex entries) of any unit
   int32_t out_leaf;    // 1 if the launch writes rows of the external vector (uses alpha/beta)
   int32_t kind;        // 0 butterfly/dense, 1 leaf solve
+  int32_t prog = 0;    // 1: a sequential program over steps [first, first+count) of the step table
 };
 
 // Per-butterfly-block bookkeeping.

@@ -34,11 +34,26 @@ struct StageArgs {
 
 constexpr int kStageThreads = 256;
 constexpr int kOutPerThread = 4;
+constexpr int kProgWaves = 8;
+constexpr int kProgThreads = 64 * kProgWaves;
+constexpr int kProgOutPerThread = 4;
+constexpr int kWaveOutPerThread = 4;
 
 // Launch helpers (defined in stage.hip).  F: factor storage, V: vectors, A: accumulation.
 hipError_t launch_stage_c64(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s);
 hipError_t launch_stage_c128(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s);
 hipError_t launch_stage_c64_hi(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s);
+// Wave-per-group variant (4 groups per workgroup, wave_lds bytes of LDS each).
+hipError_t launch_stage_wave_c64(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
+hipError_t launch_stage_wave_c128(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
+hipError_t launch_stage_wave_c64_hi(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
+// Sequential programs (sweeps over small subtrees): steps [s0, s1) of the
+// step table (3 ints per step: first unit, end unit, accumulate flag), one
+// workgroup per RHS chunk, wave_lds bytes of LDS per wave.
+hipError_t launch_program_c64(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave_lds, bool adjoint,
+                              hipStream_t s);
+hipError_t launch_program_c128(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave_lds, bool adjoint,
+                               hipStream_t s);
 
 // (nrhs, N) external layout <-> (N, R) internal layout, with dtype conversion.
 hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, int64_t n, int R, hipStream_t s);

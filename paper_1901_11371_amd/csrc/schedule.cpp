@@ -27,15 +27,18 @@ const char* last_error() { return g_err.c_str(); }
 // sweep uses the upper blocks F12^H and the upper sweep the lower blocks
 // F21^H, each traversed in reverse factor order.
 // ---------------------------------------------------------------------------
-static void sweep_rec(const Plan& P, const std::vector<int>& level_base, int dd, int64_t idx,
-                      bool lower_dir, bool adjoint, const std::vector<int32_t>& leaf_units,
-                      std::vector<Launch>& out) {
-  auto push = [&](int32_t u0, int32_t u1, int acc, int kind) {
-    Launch l;
-    l.direct = 1;
-    l.first = u0;
-    l.count = u1 - u0;
-    l.max_src = l.max_dst = l.max_mat = 0;
+namespace {
+
+struct SweepGen {
+  const Plan& P;
+  const std::vector<int>& level_base;
+  bool lower_dir, adjoint;
+  const std::vector<int32_t>& leaf_units;
+  std::vector<Launch>& out;
+  std::vector<int32_t>& steps;
+  int prog_levels;
+
+  void bound(Launch& l, int32_t u0, int32_t u1) const {
     for (int32_t u = u0; u < u1; ++u) {
       const Unit& q = P.units[u];
       const int a = q.in_len[0] + q.in_len[1], b = q.out_len[0] + q.out_len[1];
@@ -43,33 +46,68 @@ static void sweep_rec(const Plan& P, const std::vector<int>& level_base, int dd,
       l.max_dst = std::max({l.max_dst, a, b});
       l.max_mat = std::max<int32_t>(l.max_mat, q.mat_len);
     }
+  }
+  // emit one ordered step (into a program when `prog` is non-null)
+  void emit(int32_t u0, int32_t u1, int acc, int kind, Launch* prog) {
+    if (prog) {
+      steps.push_back(u0);
+      steps.push_back(u1);
+      steps.push_back(acc);
+      prog->count += 1;
+      bound(*prog, u0, u1);
+      return;
+    }
+    Launch l;
+    l.direct = 1;
+    l.first = u0;
+    l.count = u1 - u0;
+    l.max_src = l.max_dst = l.max_mat = 0;
     l.out_leaf = acc;
     l.kind = kind;
+    l.prog = 0;
+    bound(l, u0, u1);
     out.push_back(l);
-  };
-  if (dd == P.V) {
-    push(leaf_units[idx], leaf_units[idx] + 1, 0, 1);
-    return;
   }
-  const int64_t first = lower_dir ? 2 * idx : 2 * idx + 1;
-  const int64_t second = lower_dir ? 2 * idx + 1 : 2 * idx;
-  sweep_rec(P, level_base, dd + 1, first, lower_dir, adjoint, leaf_units, out);
-  const bool use_lower = (lower_dir != adjoint);
-  if (dd + 1 == P.V) {
-    const int32_t u = use_lower ? P.l0_lower_unit[idx] : P.l0_upper_unit[idx];
-    push(u, u + 1, 1, 0);
-  } else {
-    const BlockInfo& bi = P.blocks[level_base[dd + 1] + 2 * idx + (use_lower ? 1 : 0)];
-    const int nl = 2 * bi.D + 1;
-    for (int s = 0; s < nl; ++s) {
-      const int l = adjoint ? nl - 1 - s : s;
-      push(bi.lvl_begin[l], bi.lvl_end[l], s == nl - 1 ? 1 : 0, 0);
+  void rec(int dd, int64_t idx, Launch* prog) {
+    if (!prog && P.V - dd <= prog_levels) {
+      Launch l;
+      l.direct = 1;
+      l.first = static_cast<int32_t>(steps.size() / 3);
+      l.count = 0;
+      l.max_src = l.max_dst = l.max_mat = 0;
+      l.out_leaf = 1;
+      l.kind = 2;
+      l.prog = 1;
+      rec(dd, idx, &l);
+      out.push_back(l);
+      return;
     }
+    if (dd == P.V) {
+      emit(leaf_units[idx], leaf_units[idx] + 1, 0, 1, prog);
+      return;
+    }
+    const int64_t first = lower_dir ? 2 * idx : 2 * idx + 1;
+    const int64_t second = lower_dir ? 2 * idx + 1 : 2 * idx;
+    rec(dd + 1, first, prog);
+    const bool use_lower = (lower_dir != adjoint);
+    if (dd + 1 == P.V) {
+      const int32_t u = use_lower ? P.l0_lower_unit[idx] : P.l0_upper_unit[idx];
+      emit(u, u + 1, 1, 0, prog);
+    } else {
+      const BlockInfo& bi = P.blocks[level_base[dd + 1] + 2 * idx + (use_lower ? 1 : 0)];
+      const int nl = 2 * bi.D + 1;
+      for (int s = 0; s < nl; ++s) {
+        const int l = adjoint ? nl - 1 - s : s;
+        emit(bi.lvl_begin[l], bi.lvl_end[l], s == nl - 1 ? 1 : 0, 0, prog);
+      }
+    }
+    rec(dd + 1, second, prog);
   }
-  sweep_rec(P, level_base, dd + 1, second, lower_dir, adjoint, leaf_units, out);
-}
+};
 
-void build_sweeps(const Plan& P, Sweeps& S) {
+}  // namespace
+
+void build_sweeps(const Plan& P, Sweeps& S, int prog_levels) {
   std::vector<int> level_base(P.V + 1, 0);
   {
     int cur = 0;
@@ -82,14 +120,20 @@ void build_sweeps(const Plan& P, Sweeps& S) {
   S.bwd.clear();
   S.adj_fwd.clear();
   S.adj_bwd.clear();
+  S.steps.clear();
+  S.prog_levels = prog_levels;
   if (P.leaf_fwd_unit.empty()) return;
-  // P^{-1}: lower sweep with the forward leaf solves, upper with the backward ones
-  sweep_rec(P, level_base, 0, 0, true, false, P.leaf_fwd_unit, S.fwd);
-  sweep_rec(P, level_base, 0, 0, false, false, P.leaf_bwd_unit, S.bwd);
+  // P^{-1}: lower sweep with the forward leaf solves, upper with the backward ones.
   // P^{-H}: the lower sweep solves with the backward leaf matrices conjugate-
-  // transposed, the upper sweep with the forward ones
-  sweep_rec(P, level_base, 0, 0, true, true, P.leaf_bwd_unit, S.adj_fwd);
-  sweep_rec(P, level_base, 0, 0, false, true, P.leaf_fwd_unit, S.adj_bwd);
+  // transposed, the upper sweep with the forward ones.
+  SweepGen g1{P, level_base, true, false, P.leaf_fwd_unit, S.fwd, S.steps, prog_levels};
+  g1.rec(0, 0, nullptr);
+  SweepGen g2{P, level_base, false, false, P.leaf_bwd_unit, S.bwd, S.steps, prog_levels};
+  g2.rec(0, 0, nullptr);
+  SweepGen g3{P, level_base, true, true, P.leaf_bwd_unit, S.adj_fwd, S.steps, prog_levels};
+  g3.rec(0, 0, nullptr);
+  SweepGen g4{P, level_base, false, true, P.leaf_fwd_unit, S.adj_bwd, S.steps, prog_levels};
+  g4.rec(0, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,10 +237,27 @@ void unit_eval(const Plan& P, const Unit& u, bool adj, const std::vector<cplx>& 
 }  // namespace
 
 void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
-               cplx* arena, int R, cplx alpha) {
+               cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps) {
   auto bufp = [&](uint8_t id) -> cplx* { return id == BUF_X ? X : id == BUF_Y ? Y : arena; };
   std::vector<cplx> src, dst;
-  for (const Launch& L : launches) {
+  std::vector<Launch> expanded;
+  for (const Launch& L0 : launches) {
+    if (L0.prog) {
+      // a program is its steps, in order
+      for (int st = L0.first; st < L0.first + L0.count; ++st) {
+        Launch l = L0;
+        l.prog = 0;
+        l.direct = 1;
+        l.first = (*steps)[3 * st];
+        l.count = (*steps)[3 * st + 1] - (*steps)[3 * st];
+        l.out_leaf = (*steps)[3 * st + 2];
+        expanded.push_back(l);
+      }
+    } else {
+      expanded.push_back(L0);
+    }
+  }
+  for (const Launch& L : expanded) {
     for (int g = L.first; g < L.first + L.count; ++g) {
       std::vector<int32_t> us;
       if (L.direct) {
@@ -390,13 +451,13 @@ hbf_status hbf_plan_precond(const hbf_plan* plan, const double* rin, double* zou
     const bool paper = plan->prec == HBF_PREC_PAPER_TRI;
     const cplx a = paper ? P.scale : cplx(1.0);
     if (!adjoint) {
-      exec_host(P, S.fwd, false, t.data(), u.data(), arena.data(), nrhs, -a);
+      exec_host(P, S.fwd, false, t.data(), u.data(), arena.data(), nrhs, -a, &S.steps);
       cplx* mid = paper ? t.data() : u.data();
-      exec_host(P, S.bwd, false, z.data(), mid, arena.data(), nrhs, -1.0);
+      exec_host(P, S.bwd, false, z.data(), mid, arena.data(), nrhs, -1.0, &S.steps);
     } else {
-      exec_host(P, S.adj_fwd, true, u.data(), t.data(), arena.data(), nrhs, -1.0);
+      exec_host(P, S.adj_fwd, true, u.data(), t.data(), arena.data(), nrhs, -1.0, &S.steps);
       cplx* mid = paper ? t.data() : u.data();
-      exec_host(P, S.adj_bwd, true, mid, z.data(), arena.data(), nrhs, -std::conj(a));
+      exec_host(P, S.adj_bwd, true, mid, z.data(), arena.data(), nrhs, -std::conj(a), &S.steps);
     }
   }
   for (int r = 0; r < nrhs; ++r)

@@ -11,16 +11,18 @@ namespace hbf {
 struct Sweeps {
   std::vector<Launch> fwd, bwd;          // P^{-1}: lower then upper substitution
   std::vector<Launch> adj_fwd, adj_bwd;  // P^{-H}
+  std::vector<int32_t> steps;            // program steps: (first unit, end unit, accumulate)
+  int prog_levels = 6;                   // subtrees of <= 2^prog_levels leaves run as one program
 };
 
-void build_sweeps(const Plan& P, Sweeps& S);
+void build_sweeps(const Plan& P, Sweeps& S, int prog_levels = 6);
 
 // Run a schedule on host buffers in the internal (rows, R) layout.  In
 // adjoint mode every unit reads its forward output segments and writes its
 // forward input segments.  Launches with out_leaf set add alpha * result to
 // the destination; the others overwrite it.
 void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
-               cplx* arena, int R, cplx alpha);
+               cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps = nullptr);
 
 void host_leaf_factor(Plan& P, hbf_prec prec);
 

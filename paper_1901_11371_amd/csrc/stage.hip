@@ -49,21 +49,24 @@ __device__ __forceinline__ int ceil_div_pos(int a, int b) {  // ceil(a/b) for b 
   return a <= 0 ? 0 : (a + b - 1) / b;
 }
 
-template <class F, class V, class A, bool ADJ>
-__global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x;
-  const int gi = blockIdx.x / a.nchunks;
-  const int chunk = blockIdx.x - gi * a.nchunks;
-  const int g = a.first + gi;
-  int q0, q1;
-  if (a.direct) {
-    q0 = g;
-    q1 = g + 1;
-  } else {
-    q0 = a.gofs[g];
-    q1 = a.gofs[g + 1];
+// Synchronisation of a team: the whole workgroup, or one wavefront.
+struct BlockSync {
+  __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+struct WaveSync {
+  __device__ __forceinline__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+};
+
+// One team (TEAM threads) evaluates the group of units [q0, q1) (unit ids
+// q directly, or through the group table) for RHS chunk `chunk` and writes
+// its destination.  smem is the team's LDS region.
+template <class F, class V, class A, bool ADJ, int TEAM, int OPT, class Sync>
+__device__ __forceinline__ void process_group(const StageArgs& a, int q0, int q1, bool direct, int chunk, int tid,
+                                              unsigned char* smem, Sync sync) {
   const int r0 = chunk * a.rc;
   const int nr = min(a.rc, a.R - r0);
   const int R = a.R;
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
   uint8_t* s_q = s_p + 512;                                  // their inverses, 2 x 256
 
   // destination segments (shared by all units of the group)
-  const Unit* U0 = &a.units[a.direct ? q0 : a.gunits[q0]];
+  const Unit* U0 = &a.units[direct ? q0 : a.gunits[q0]];
   const int d_buf = ADJ ? U0->in_buf : U0->out_buf;
   const int d_off0 = ADJ ? U0->in_off[0] : U0->out_off[0];
   const int d_off1 = ADJ ? U0->in_off[1] : U0->out_off[1];
@@ -83,12 +86,12 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
   const int n_dst = d_len0 + d_len1;
   const int n_out = n_dst * nr;
 
-  cx<A> acc[kOutPerThread];
+  cx<A> acc[OPT];
 #pragma unroll
-  for (int j = 0; j < kOutPerThread; ++j) acc[j] = cx<A>{0, 0};
+  for (int j = 0; j < OPT; ++j) acc[j] = cx<A>{0, 0};
 
   for (int q = q0; q < q1; ++q) {
-    const Unit* U = &a.units[a.direct ? q : a.gunits[q]];
+    const Unit* U = &a.units[direct ? q : a.gunits[q]];
     const int type = U->type;
     const int s_buf = ADJ ? U->out_buf : U->in_buf;
     const int s_off0 = ADJ ? U->out_off[0] : U->in_off[0];
@@ -102,11 +105,11 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
     const int64_t mat = U->mat;
     const int mat_len = U->mat_len;
 
-    __syncthreads();  // LDS of the previous unit is free
+    sync();  // LDS of the previous unit is free
     // stage the sources
     {
       const V* sb = reinterpret_cast<const V*>(a.buf[s_buf]);
-      for (int e = tid; e < n_src * nr; e += kStageThreads) {
+      for (int e = tid; e < n_src * nr; e += TEAM) {
         const int t = e / nr;
         const int rr = e - t * nr;
         const int row = (t < s_len0) ? s_off0 + t : s_off1 + (t - s_len0);
@@ -119,7 +122,7 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
     else if (type == UNIT_SCATTER) plen = f_out;
     if (plen) {
       const uint8_t* pp = a.perm + U->perm;
-      for (int e = tid; e < 2 * plen; e += kStageThreads) {
+      for (int e = tid; e < 2 * plen; e += TEAM) {
         const int o = e / plen, j = e - o * plen;
         const uint8_t v = pp[e];
         s_p[o * 256 + j] = v;
@@ -130,18 +133,18 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
     const cx<F>* gm = reinterpret_cast<const cx<F>*>(a.fac) + mat;
     for (int e0 = 0; e0 < mat_len; e0 += a.ch) {
       const int e1 = min(mat_len, e0 + a.ch);
-      __syncthreads();
+      sync();
       {
         const u32x4* g4 = reinterpret_cast<const u32x4*>(gm + e0);
         u32x4* l4 = reinterpret_cast<u32x4*>(s_mat);
         const int nw = ((e1 - e0) * static_cast<int>(sizeof(cx<F>)) + 15) / 16;
-        for (int w = tid; w < nw; w += kStageThreads) l4[w] = __builtin_nontemporal_load(&g4[w]);
+        for (int w = tid; w < nw; w += TEAM) l4[w] = __builtin_nontemporal_load(&g4[w]);
       }
-      __syncthreads();
+      sync();
       const bool first_chunk = (e0 == 0);
 #pragma unroll
-      for (int j = 0; j < kOutPerThread; ++j) {
-        const int p = tid + j * kStageThreads;
+      for (int j = 0; j < OPT; ++j) {
+        const int p = tid + j * TEAM;
         if (p >= n_out) break;
         const int o = p / nr;
         const int rr = p - o * nr;
@@ -247,8 +250,8 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
   V* db = reinterpret_cast<V*>(a.buf[d_buf]);
   const A are = static_cast<A>(a.alpha_re), aim = static_cast<A>(a.alpha_im);
 #pragma unroll
-  for (int j = 0; j < kOutPerThread; ++j) {
-    const int p = tid + j * kStageThreads;
+  for (int j = 0; j < OPT; ++j) {
+    const int p = tid + j * TEAM;
     if (p >= n_out) break;
     const int o = p / nr;
     const int rr = p - o * nr;
@@ -262,6 +265,101 @@ __global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
     using VT = decltype(dp->x);
     *dp = V{static_cast<VT>(v.x), static_cast<VT>(v.y)};
   }
+}
+
+template <class F, class V, class A, bool ADJ>
+__global__ void __launch_bounds__(kStageThreads) k_stage(StageArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int gi = blockIdx.x / a.nchunks;
+  const int chunk = blockIdx.x - gi * a.nchunks;
+  const int g = a.first + gi;
+  int q0, q1;
+  if (a.direct) {
+    q0 = g;
+    q1 = g + 1;
+  } else {
+    q0 = a.gofs[g];
+    q1 = a.gofs[g + 1];
+  }
+  process_group<F, V, A, ADJ, kStageThreads, kOutPerThread>(a, q0, q1, a.direct != 0, chunk, threadIdx.x, smem,
+                                                            BlockSync{});
+}
+
+// Wave-per-group variant: each of the 4 waves of a workgroup evaluates its own
+// group with its own LDS slice (more independent factor streams in flight
+// when one group's matrices are small, e.g. one right-hand side).
+template <class F, class V, class A, bool ADJ>
+__global__ void __launch_bounds__(kStageThreads) k_stage_wave(StageArgs a, int ngroups, int wave_lds) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x - wave * 64;
+  const int gt = blockIdx.x * (kStageThreads / 64) + wave;
+  if (gt >= ngroups * a.nchunks) return;
+  const int gi = gt / a.nchunks;
+  const int chunk = gt - gi * a.nchunks;
+  const int g = a.first + gi;
+  int q0, q1;
+  if (a.direct) {
+    q0 = g;
+    q1 = g + 1;
+  } else {
+    q0 = a.gofs[g];
+    q1 = a.gofs[g + 1];
+  }
+  process_group<F, V, A, ADJ, 64, kWaveOutPerThread>(a, q0, q1, a.direct != 0, chunk, lane,
+                                                     smem + static_cast<size_t>(wave) * wave_lds, WaveSync{});
+}
+
+// A sequential program of steps run by one workgroup per RHS chunk: each step
+// is a range of independent units (one block level, a dense neighbour block or
+// a leaf solve); the waves take the units of a step round-robin, and the
+// workgroup synchronises between steps.  Used for the sweeps over subtrees
+// whose blocks are too small to fill the GPU.
+template <class F, class V, class A, bool ADJ>
+__global__ void __launch_bounds__(kProgThreads) k_program(StageArgs a, const int32_t* steps, int s0, int s1,
+                                                          int wave_lds) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x - wave * 64;
+  unsigned char* my = smem + static_cast<size_t>(wave) * wave_lds;
+  const int chunk = blockIdx.x;
+  const double are = a.alpha_re, aim = a.alpha_im;
+  for (int st = s0; st < s1; ++st) {
+    const int u0 = steps[3 * st], u1 = steps[3 * st + 1], acc = steps[3 * st + 2];
+    StageArgs b = a;
+    b.acc = acc;
+    b.alpha_re = acc ? are : 0.0;
+    b.alpha_im = acc ? aim : 0.0;
+    for (int u = u0 + wave; u < u1; u += kProgWaves)
+      process_group<F, V, A, ADJ, 64, kProgOutPerThread>(b, u, u + 1, true, chunk, lane, my, WaveSync{});
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+template <class F, class V, class A>
+hipError_t launch_program(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave_lds, bool adjoint,
+                          hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.nchunks));
+  const size_t lds = static_cast<size_t>(wave_lds) * kProgWaves;
+  if (adjoint)
+    hipLaunchKernelGGL((k_program<F, V, A, true>), grid, dim3(kProgThreads), lds, s, a, steps, s0, s1, wave_lds);
+  else
+    hipLaunchKernelGGL((k_program<F, V, A, false>), grid, dim3(kProgThreads), lds, s, a, steps, s0, s1, wave_lds);
+  return hipGetLastError();
+}
+
+template <class F, class V, class A>
+hipError_t launch_stage_wave(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s) {
+  const int per = kStageThreads / 64;
+  const int64_t teams = static_cast<int64_t>(ngroups) * a.nchunks;
+  const dim3 grid(static_cast<unsigned>((teams + per - 1) / per));
+  const size_t lds = static_cast<size_t>(wave_lds) * per;
+  if (adjoint)
+    hipLaunchKernelGGL((k_stage_wave<F, V, A, true>), grid, dim3(kStageThreads), lds, s, a, ngroups, wave_lds);
+  else
+    hipLaunchKernelGGL((k_stage_wave<F, V, A, false>), grid, dim3(kStageThreads), lds, s, a, ngroups, wave_lds);
+  return hipGetLastError();
 }
 
 template <class F, class V, class A>
@@ -435,6 +533,23 @@ hipError_t launch_stage_c128(const StageArgs& a, int ngroups, bool adjoint, size
 }
 hipError_t launch_stage_c64_hi(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s) {
   return launch_stage<float, cd, double>(a, ngroups, adjoint, lds, s);
+}
+hipError_t launch_stage_wave_c64(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s) {
+  return launch_stage_wave<float, cf, float>(a, ngroups, wave_lds, adjoint, s);
+}
+hipError_t launch_stage_wave_c128(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s) {
+  return launch_stage_wave<double, cd, double>(a, ngroups, wave_lds, adjoint, s);
+}
+hipError_t launch_stage_wave_c64_hi(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s) {
+  return launch_stage_wave<float, cd, double>(a, ngroups, wave_lds, adjoint, s);
+}
+hipError_t launch_program_c64(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave_lds, bool adjoint,
+                              hipStream_t s) {
+  return launch_program<float, cf, float>(a, steps, s0, s1, wave_lds, adjoint, s);
+}
+hipError_t launch_program_c128(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave_lds, bool adjoint,
+                               hipStream_t s) {
+  return launch_program<double, cd, double>(a, steps, s0, s1, wave_lds, adjoint, s);
 }
 
 hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, int64_t n, int R, hipStream_t s) {

@@ -27,14 +27,15 @@ def _curve_struct(curves):
     return cs, (xy, off)
 
 
-def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, nthreads=0, eta0=0.0):
+def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, nthreads=0, eta0=0.0,
+          cache_plan=0):
     keep = []
     zp = None
     if z is not None:
         zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
         keep.append(zz)
         zp = zz.ctypes.data_as(C.POINTER(C.c_double))
-    o = _capi.BuildOpts(DTYPE[dtype], PREC[prec], eta0, zp, max_nrhs, restart, device, nthreads)
+    o = _capi.BuildOpts(DTYPE[dtype], PREC[prec], eta0, zp, max_nrhs, restart, device, nthreads, cache_plan)
     return o, keep
 
 
@@ -108,14 +109,15 @@ class Context:
     device, shape (N,) or (nrhs, N), complex64 or complex128."""
 
     def __init__(self, curves, kappa, leaf, tol, dtype="c64", prec="block", z=None, max_nrhs=1, restart=30,
-                 device=0, nthreads=0):
+                 device=0, nthreads=0, cache_plan=False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("hbf.Context needs a HIP device")
         self.lib = _capi.load()
         self.device = torch.device("cuda", device)
         cs, keep = _curve_struct(curves)
-        o, k2 = _opts(dtype, prec, z, max_nrhs=max_nrhs, restart=restart, device=device, nthreads=nthreads)
+        o, k2 = _opts(dtype, prec, z, max_nrhs=max_nrhs, restart=restart, device=device, nthreads=nthreads,
+                      cache_plan=int(cache_plan))
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))
         del keep, k2

@@ -39,8 +39,9 @@ def _rel(a, b):
 
 
 @pytest.fixture(scope="module")
-def spiral(torch):
-    c = inputs.archimedean_spiral(4096)
+def semi(torch):
+    # non-resonant open arc: the preconditioned iteration count stays small (Sec. 4)
+    c = inputs.semicircle(4096)
     rho, w = efie.segments(c.xy, c.node_off)
     return c, efie.dense_A(rho, w, KAPPA)
 
@@ -63,11 +64,11 @@ def test_plain_strip_c128_vs_dense_lu(torch):
 
 
 @pytest.mark.parametrize("prec", ["block", "paper"])
-def test_mixed_c64_batched_vs_dense_lu(torch, spiral, prec):
-    c, A = spiral
+def test_mixed_c64_batched_vs_dense_lu(torch, semi, prec):
+    c, A = semi
     angles = inputs.uniform_angles(6)
     B = inputs.plane_wave_rhs(c, angles)
-    _say(f"[solve] spiral N=4096 c64 mixed, 6 RHS, prec={prec}")
+    _say(f"[solve] semicircle N=4096 c64 mixed, 6 RHS, prec={prec}")
     ctx = _ctx(c, "c64", prec=prec)
     X, info, st = ctx.solve(torch.tensor(B, device="cuda"), tol=1e-6)
     X = X.cpu().numpy()
@@ -82,10 +83,10 @@ def test_mixed_c64_batched_vs_dense_lu(torch, spiral, prec):
     ctx.close()
 
 
-def test_adjoint_solve_vs_dense(torch, spiral):
-    c, A = spiral
+def test_adjoint_solve_vs_dense(torch, semi):
+    c, A = semi
     g = inputs.random_complex((2, 4096), 41)
-    _say("[adjoint solve] spiral c128")
+    _say("[adjoint solve] semicircle c128")
     ctx = _ctx(c, "c128")
     lam, info, st = ctx.solve_adjoint(torch.tensor(g, device="cuda"), tol=1e-8)
     lam = lam.cpu().numpy()
@@ -96,8 +97,8 @@ def test_adjoint_solve_vs_dense(torch, spiral):
     ctx.close()
 
 
-def test_preconditioner_reduces_iterations(torch, spiral):
-    c, _ = spiral
+def test_preconditioner_reduces_iterations(torch, semi):
+    c, _ = semi
     b = inputs.plane_wave_rhs(c, [0.4])[0]
     it = {}
     for prec in ("block", "none"):
@@ -106,12 +107,12 @@ def test_preconditioner_reduces_iterations(torch, spiral):
         it[prec] = info[0]["iters"]
         ctx.close()
     _say(f"[iterations] with {it['block']} without {it['none']}")
-    assert it["block"] < it["none"]
+    assert it["block"] < 15 and it["block"] * 5 < it["none"]
 
 
-def test_solve_failure_paths(torch, spiral):
+def test_solve_failure_paths(torch, semi):
     from paper_1901_11371_amd._capi import HBF_EINVAL, HBF_NOCONV, HbfError
-    c, _ = spiral
+    c, _ = semi
     ctx = _ctx(c, "c128")
     b = inputs.plane_wave_rhs(c, [0.1])[0]
     x, info, st = ctx.solve(torch.tensor(b, device="cuda"), tol=1e-12, max_iters=1, max_refine=1)
