@@ -160,6 +160,21 @@ hbf_status hbf_solve(hbf_ctx* ctx, const void* b, void* x, int32_t nrhs, hbf_dty
 hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrhs, hbf_dtype io,
                              const hbf_solve_opts* opts, hbf_solve_info* info, void* stream);
 
+/* Set an execution parameter of the context (used by the autotuner; results
+ * do not depend on them beyond rounding):
+ *   "prog_levels"   subtrees of <= 2^value leaves are swept by one workgroup
+ *                   program (0..12; default 6),
+ *   "pipe_max_r"    stage launches with nrhs <= value use pipelined wave teams
+ *                   (default 4),
+ *   "prog_pipe"     1 = pipelined wave teams inside the sweep programs,
+ *   "r1_kernel"     1 = register-streaming kernel with LDS atomics for one-RHS
+ *                   stages (when pipe_max_r is 0),
+ *   "r1_max_blocks" persistent grid size (workgroups) of the one-RHS kernels,
+ *   "wave_units"    1 = one wave per unit for two-RHS stages,
+ *   "use_graphs"    1 = replay the preconditioner sweeps from HIP graphs.
+ * Unknown keys or out-of-range values return HBF_EINVAL. */
+hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);
+
 /* Sizes and ranks of the built factorisation. */
 hbf_status hbf_stats(const hbf_ctx* ctx, hbf_stats_t* out);
 

@@ -58,6 +58,7 @@ SIGNATURES = {
     "hbf_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int,
                                     C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p]),
     "hbf_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "hbf_tune": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "hbf_size": (C.c_int64, [C.c_void_p]),
     "hbf_free": (None, [C.c_void_p]),
     "hbf_last_error": (C.c_char_p, []),

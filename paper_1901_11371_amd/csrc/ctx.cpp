@@ -8,6 +8,8 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <atomic>
+#include <thread>
 #include <stdexcept>
 #include <string>
 
@@ -40,7 +42,15 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+void free_graphs(hbf_ctx* c) {
+  for (auto& kv : c->pc_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->pc_graphs.clear();
+}
+
 void free_device(hbf_ctx* c) {
+  free_graphs(c);
+  dfree(c->d_pz);
+  c->d_pz = nullptr;
   dfree(c->d_fac);
   dfree(c->d_perm);
   dfree(c->d_units);
@@ -92,46 +102,81 @@ void upload_factors(hbf_ctx* c, int64_t begin, int64_t end, hipStream_t s) {
   (void)hipHostFree(stage);
 }
 
-// FP64 leaf blocks with the current impedance -> device, and factorise them.
-void factor_leaves(hbf_ctx* c, hipStream_t s) {
-  if (c->prec == HBF_PREC_NONE || c->P.leaf_fwd_unit.empty()) return;
-  const int n0 = c->P.n0;
-  const int64_t nl = c->n / n0;
-  const int64_t bs = static_cast<int64_t>(n0) * n0;
-  std::vector<cd> D(c->diag_noz.size());
-  for (int64_t b = 0; b < nl; ++b) {
-    for (int64_t e = 0; e < bs; ++e) D[b * bs + e] = c->diag_noz[b * bs + e];
-    if (!c->P.z.empty())
-      for (int i = 0; i < n0; ++i) {
-        cd& d = D[b * bs + static_cast<int64_t>(i) * n0 + i];
-        d.x += c->P.z[b * n0 + i].real();
-        d.y += c->P.z[b * n0 + i].imag();
+// Exact FP64 diagonal blocks of the super-leaves without z (row-major ns x ns),
+// cached on the host for refactoring.
+void superleaf_entries(hbf_ctx* c) {
+  const Plan& P = c->P;
+  const int64_t ns = static_cast<int64_t>(P.n0) << P.sl;
+  const int64_t nsl = P.n / ns;
+  c->sl_noz.assign(static_cast<size_t>(nsl * ns * ns), cd{0, 0});
+  const int T = std::max(1, build_threads(nullptr));
+  std::vector<std::thread> th;
+  std::atomic<int64_t> next(0);
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&]() {
+      for (;;) {
+        const int64_t S = next.fetch_add(1);
+        if (S >= nsl) return;
+        for (int64_t i = 0; i < ns; ++i)
+          for (int64_t j = 0; j < ns; ++j) {
+            cplx v = (i == j) ? P.self_entry(S * ns + i) : P.entry(S * ns + i, S * ns + j);
+            if (i == j && !P.z.empty()) v -= P.z[S * ns + i];
+            c->sl_noz[(S * ns + i) * ns + j] = cd{v.real(), v.imag()};
+          }
       }
-  }
-  hip_check(hipMemcpyAsync(c->d_diag64, D.data(), D.size() * sizeof(cd), hipMemcpyHostToDevice, s), "upload leaves");
-  hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int), s), "memset flag");
-  const int64_t batch = std::min<int64_t>(nl, 1024);
+    });
+  for (auto& x : th) x.join();
+}
+
+// Super-leaf inverses with the current impedance, computed on the device in FP64.
+void factor_leaves(hbf_ctx* c, hipStream_t s) {
+  if (c->prec == HBF_PREC_NONE || c->P.sl_fwd.empty()) return;
+  const Plan& P = c->P;
+  const int n0 = P.n0;
+  const int64_t ns = static_cast<int64_t>(n0) << P.sl;
+  const int64_t nsl = P.n / ns;
+  const int64_t blk = ns * ns;
+  const int64_t batch = std::min<int64_t>(nsl, 64);
+  SuperleafOut so;
+  const int64_t per = static_cast<int64_t>(n0) * n0 * (1 << P.sl) * ((1 << P.sl) + 1) / 2;
+  so.per_superleaf = per;
+  for (int set = 0; set < 4; ++set) so.base[set] = P.leaf_fac_begin + set * nsl * per;
+  cd* dA = nullptr;
   cd* work = nullptr;
-  dmalloc(&work, static_cast<size_t>(batch) * 2 * bs * sizeof(cd), "leaf work");
+  hip_check(hipMemsetAsync(c->d_flag, 0, sizeof(int), s), "memset flag");
+  dmalloc(&dA, static_cast<size_t>(batch * blk) * sizeof(cd), "superleaf blocks");
   try {
-    const Unit& uf = c->P.units[c->P.leaf_fwd_unit[0]];
-    const Unit& ub = c->P.units[c->P.leaf_bwd_unit[0]];
-    const int64_t stride = uf.mat_len;
+    dmalloc(&work, static_cast<size_t>(batch * 3 * blk) * sizeof(cd), "superleaf work");
+    std::vector<cd> H(static_cast<size_t>(batch * blk));
     const int mode = (c->prec == HBF_PREC_PAPER_TRI) ? 1 : 0;
-    for (int64_t b0 = 0; b0 < nl; b0 += batch) {
-      const int64_t nb = std::min(batch, nl - b0);
-      hip_check(launch_leaf_factor(c->d_diag64, b0, nb, n0, mode, c->P.scale.real(), c->P.scale.imag(), c->d_fac,
-                                   c->dtype == HBF_C128, uf.mat, ub.mat, stride, c->d_flag, work, s),
-                "leaf factor");
+    for (int64_t S0 = 0; S0 < nsl; S0 += batch) {
+      const int64_t nb = std::min(batch, nsl - S0);
+      std::memcpy(H.data(), &c->sl_noz[S0 * blk], static_cast<size_t>(nb * blk) * sizeof(cd));
+      if (!P.z.empty())
+        for (int64_t b = 0; b < nb; ++b)
+          for (int64_t i = 0; i < ns; ++i) {
+            cd& d = H[b * blk + i * ns + i];
+            d.x += P.z[(S0 + b) * ns + i].real();
+            d.y += P.z[(S0 + b) * ns + i].imag();
+          }
+      hip_check(hipMemcpyAsync(dA, H.data(), static_cast<size_t>(nb * blk) * sizeof(cd), hipMemcpyHostToDevice, s),
+                "upload superleaf");
+      hip_check(launch_superleaf_factor(dA, S0, nb, static_cast<int>(ns), n0, mode, P.scale.real(), P.scale.imag(),
+                                        c->d_fac, c->dtype == HBF_C128, so, c->d_flag, work, s),
+                "superleaf factor");
+      hip_check(hipStreamSynchronize(s), "superleaf sync");
     }
     int flag = 0;
     hip_check(hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s), "flag");
     hip_check(hipStreamSynchronize(s), "leaf sync");
     dfree(work);
+    dfree(dA);
     work = nullptr;
+    dA = nullptr;
     if (flag) throw std::domain_error("a leaf block is singular to working precision");
   } catch (...) {
     dfree(work);
+    dfree(dA);
     throw;
   }
 }
@@ -188,7 +233,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
   const int ch_cap = static_cast<int>(32768 / szF);
   for (const Launch& l : L) {
     if (l.prog) {
-      // one workgroup per RHS chunk; each wave owns an LDS slice
+      // one workgroup per RHS chunk; each wave is a pipelined team
       StageArgs a;
       a.units = c->d_units;
       a.gofs = c->d_gofs;
@@ -201,24 +246,35 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.first = 0;
       a.direct = 1;
       a.R = R;
-      const int md = std::max(1, l.max_dst);
-      int rc = std::min(R, std::max(1, (64 * kProgOutPerThread) / md));
-      const int wave_lds = 8192;
-      while (rc > 1 && static_cast<size_t>(l.max_src) * rc * szA > 2048) --rc;
+      const int mx = std::max({1, l.max_dst, l.max_src});
+      const int rc = std::min(R, std::max(1, 256 / mx));
       a.rc = rc;
       a.nchunks = (R + rc - 1) / rc;
       a.acc = 0;
       a.alpha_re = alpha_re;
       a.alpha_im = alpha_im;
-      a.src_cap = std::max(1, l.max_src * rc);
-      int ch = static_cast<int>((wave_lds - 1024 - static_cast<size_t>(a.src_cap) * szA) / szF);
-      ch &= ~1;
-      ch = std::min(ch, (l.max_mat + 1) & ~1);
-      if (ch < 2) ch = 2;
-      a.ch = ch;
-      hipError_t e = (c->dtype == HBF_C128)
-                         ? launch_program_c128(a, c->d_steps, l.first, l.first + l.count, wave_lds, adjoint, s)
-                         : launch_program_c64(a, c->d_steps, l.first, l.first + l.count, wave_lds, adjoint, s);
+      a.src_cap = 0;
+      a.ch = 0;
+      hipError_t e;
+      if (c->prog_pipe) {
+        e = (c->dtype == HBF_C128) ? launch_prog_pipe_c128(a, c->d_steps, l.first, l.first + l.count, adjoint, s)
+                                   : launch_prog_pipe_c64(a, c->d_steps, l.first, l.first + l.count, adjoint, s);
+      } else {
+        const int mdo = std::max(1, l.max_dst);
+        int rc2 = std::min(R, std::max(1, (64 * kProgOutPerThread) / mdo));
+        const int wave_lds = 8192;
+        while (rc2 > 1 && static_cast<size_t>(l.max_src) * rc2 * szA > 2048) --rc2;
+        a.rc = rc2;
+        a.nchunks = (R + rc2 - 1) / rc2;
+        a.src_cap = std::max(1, l.max_src * rc2);
+        int ch = static_cast<int>((wave_lds - 1024 - static_cast<size_t>(a.src_cap) * szA) / szF);
+        ch &= ~1;
+        ch = std::min(ch, (l.max_mat + 1) & ~1);
+        if (ch < 2) ch = 2;
+        a.ch = ch;
+        e = (c->dtype == HBF_C128) ? launch_program_c128(a, c->d_steps, l.first, l.first + l.count, wave_lds, adjoint, s)
+                                   : launch_program_c64(a, c->d_steps, l.first, l.first + l.count, wave_lds, adjoint, s);
+      }
       if (e != hipSuccess) return e;
       continue;
     }
@@ -235,6 +291,39 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     a.direct = l.direct;
     a.R = R;
     const int md = std::max(1, l.max_dst);
+    const bool adj = adjoint && !l.force_fwd;
+    const int mxp = std::max({1, l.max_dst, l.max_src});
+    if (R <= c->pipe_max_r && mxp <= 256) {
+      const int rc = std::min(R, std::max(1, 256 / mxp));
+      a.rc = rc;
+      a.nchunks = (R + rc - 1) / rc;
+      a.acc = l.out_leaf;
+      a.alpha_re = alpha_re;
+      a.alpha_im = alpha_im;
+      a.src_cap = 0;
+      a.ch = 0;
+      hipError_t e;
+      if (c->dtype == HBF_C128) e = launch_pipe_c128(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
+      else if (vec_c128) e = launch_pipe_c64_hi(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
+      else e = launch_pipe_c64(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    if (R == 1 && c->r1_kernel && l.max_src <= 255 && l.max_dst <= 256) {
+      a.rc = 1;
+      a.nchunks = 1;
+      a.acc = l.out_leaf;
+      a.alpha_re = alpha_re;
+      a.alpha_im = alpha_im;
+      a.src_cap = 0;
+      a.ch = 0;
+      hipError_t e;
+      if (c->dtype == HBF_C128) e = launch_stage_r1_c128(a, l.count, adj, c->r1_max_blocks, s);
+      else if (vec_c128) e = launch_stage_r1_c64_hi(a, l.count, adj, c->r1_max_blocks, s);
+      else e = launch_stage_r1_c64(a, l.count, adj, c->r1_max_blocks, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (c->wave_units && md * std::min(R, 2) <= 64 * kWaveOutPerThread && R <= 2) {
       // small groups: one wave per group
       a.rc = R;
@@ -250,9 +339,9 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       if (ch < 2) ch = 2;
       a.ch = ch;
       hipError_t e;
-      if (c->dtype == HBF_C128) e = launch_stage_wave_c128(a, l.count, wave_lds, adjoint, s);
-      else if (vec_c128) e = launch_stage_wave_c64_hi(a, l.count, wave_lds, adjoint, s);
-      else e = launch_stage_wave_c64(a, l.count, wave_lds, adjoint, s);
+      if (c->dtype == HBF_C128) e = launch_stage_wave_c128(a, l.count, wave_lds, adj, s);
+      else if (vec_c128) e = launch_stage_wave_c64_hi(a, l.count, wave_lds, adj, s);
+      else e = launch_stage_wave_c64(a, l.count, wave_lds, adj, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -269,9 +358,9 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     a.src_cap = std::max(1, l.max_src * rc);
     const size_t lds = static_cast<size_t>(a.src_cap) * szA + static_cast<size_t>(ch) * szF + 1024;
     hipError_t e;
-    if (c->dtype == HBF_C128) e = launch_stage_c128(a, l.count, adjoint, lds, s);
-    else if (vec_c128) e = launch_stage_c64_hi(a, l.count, adjoint, lds, s);
-    else e = launch_stage_c64(a, l.count, adjoint, lds, s);
+    if (c->dtype == HBF_C128) e = launch_stage_c128(a, l.count, adj, lds, s);
+    else if (vec_c128) e = launch_stage_c64_hi(a, l.count, adj, lds, s);
+    else e = launch_stage_c64(a, l.count, adj, lds, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -285,7 +374,33 @@ hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c1
   return HBF_OK;
 }
 
+// The two sweeps of the preconditioner (input in d_u, output in zout).
+static hipError_t enqueue_sweeps(hbf_ctx* c, void* zout, int R, bool adjoint, hipStream_t s) {
+  const bool paper = c->prec == HBF_PREC_PAPER_TRI;
+  const double are = paper ? c->P.scale.real() : 1.0, aim = paper ? c->P.scale.imag() : 0.0;
+  const bool v128 = c->dtype == HBF_C128;
+  hipError_t e;
+  if (!adjoint) {
+    e = run_launches(c, c->S.fwd, false, c->d_t, c->d_u, R, v128, -are, -aim, s);
+    if (e == hipSuccess && !paper) e = run_launches(c, c->S.diag, false, c->d_t, c->d_u, R, v128, 1.0, 0.0, s);
+    if (e == hipSuccess) {
+      void* mid = paper ? c->d_t : c->d_u;
+      e = run_launches(c, c->S.bwd, false, zout, mid, R, v128, -1.0, 0.0, s);
+    }
+  } else {
+    e = run_launches(c, c->S.adj_fwd, true, c->d_u, c->d_t, R, v128, -1.0, 0.0, s);
+    if (e == hipSuccess && !paper) e = run_launches(c, c->S.diag, true, c->d_u, c->d_t, R, v128, 1.0, 0.0, s);
+    if (e == hipSuccess) {
+      void* mid = paper ? c->d_t : c->d_u;
+      e = run_launches(c, c->S.adj_bwd, true, mid, zout, R, v128, -are, aim, s);
+    }
+  }
+  return e;
+}
+
 // z = P^{-1} r (or P^{-H} r); r, z internal layout, vector dtype = context dtype.
+// The sweep launches are captured once per (nrhs, adjoint) into a HIP graph and
+// replayed; the graph reads d_u and writes d_pz, copied in and out around it.
 hbf_status precond_internal(hbf_ctx* c, const void* rin, void* zout, int R, bool adjoint, hipStream_t s) {
   const size_t bytes = static_cast<size_t>(c->n) * R * c->elt;
   hipError_t e = hipMemcpyAsync(c->d_u, rin, bytes, hipMemcpyDeviceToDevice, s);
@@ -294,23 +409,34 @@ hbf_status precond_internal(hbf_ctx* c, const void* rin, void* zout, int R, bool
     e = hipMemcpyAsync(zout, c->d_u, bytes, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? HBF_OK : fail(HBF_EHIP, "precond copy");
   }
-  const bool paper = c->prec == HBF_PREC_PAPER_TRI;
-  const double are = paper ? c->P.scale.real() : 1.0, aim = paper ? c->P.scale.imag() : 0.0;
-  const bool v128 = c->dtype == HBF_C128;
-  if (!adjoint) {
-    e = run_launches(c, c->S.fwd, false, c->d_t, c->d_u, R, v128, -are, -aim, s);
-    if (e == hipSuccess) {
-      void* mid = paper ? c->d_t : c->d_u;
-      e = run_launches(c, c->S.bwd, false, zout, mid, R, v128, -1.0, 0.0, s);
-    }
-  } else {
-    e = run_launches(c, c->S.adj_fwd, true, c->d_u, c->d_t, R, v128, -1.0, 0.0, s);
-    if (e == hipSuccess) {
-      void* mid = paper ? c->d_t : c->d_u;
-      e = run_launches(c, c->S.adj_bwd, true, mid, zout, R, v128, -are, aim, s);
-    }
+  if (!c->use_graphs) {
+    e = enqueue_sweeps(c, zout, R, adjoint, s);
+    if (e != hipSuccess) return fail(HBF_EHIP, std::string("precond launch: ") + hipGetErrorString(e));
+    return HBF_OK;
   }
-  if (e != hipSuccess) return fail(HBF_EHIP, std::string("precond launch: ") + hipGetErrorString(e));
+  const auto key = std::make_pair(R, adjoint ? 1 : 0);
+  auto it = c->pc_graphs.find(key);
+  if (it == c->pc_graphs.end()) {
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(HBF_EHIP, "graph stream");
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = enqueue_sweeps(c, c->d_pz, R, adjoint, cs);
+      e = hipStreamEndCapture(cs, &g);
+      if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(HBF_EHIP, std::string("precond graph: ") + hipGetErrorString(e));
+    it = c->pc_graphs.emplace(key, ge).first;
+  }
+  e = hipGraphLaunch(it->second, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(zout, c->d_pz, bytes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(HBF_EHIP, std::string("precond graph launch: ") + hipGetErrorString(e));
   return HBF_OK;
 }
 
@@ -334,7 +460,7 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       return fail(HBF_EINVAL, "hbf_build: bad preconditioner");
     if (leaf > 64) return fail(HBF_EINVAL, "hbf_build: the device path supports leaf <= 64");
     c->max_nrhs = (opts && opts->max_nrhs > 0) ? opts->max_nrhs : 1;
-    c->restart = (opts && opts->restart > 0) ? opts->restart : 30;
+    c->restart = (opts && opts->restart > 0) ? std::min(opts->restart, 255) : 30;
     c->device = opts ? opts->device : 0;
     c->elt = c->dtype == HBF_C64 ? 8 : 16;
     int ndev = 0;
@@ -417,18 +543,20 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     dmalloc(&c->d_vout, vbytes, "vectors");
     dmalloc(&c->d_u, vbytes, "vectors");
     dmalloc(&c->d_t, vbytes, "vectors");
-    dmalloc(&c->d_diag64, static_cast<size_t>(nl * bs) * sizeof(cd), "leaves");
+    dmalloc(&c->d_pz, vbytes, "vectors");
     dmalloc(&c->d_flag, 256, "flag");
     // solver workspace (inner Krylov basis in the context dtype, FP64 outer vectors)
     dmalloc(&c->d_krylov, static_cast<size_t>(c->restart + 1) * N * R * c->elt, "krylov");
     dmalloc(&c->d_w, static_cast<size_t>(N) * R * c->elt, "krylov");
     dmalloc(&c->d_x64, 4 * vbytes, "solver vectors");
-    c->red_len = static_cast<size_t>(2 * (c->restart + 2)) * R * 1024;
+    c->red_len = static_cast<size_t>(2 * 34) * R * 1024;
     dmalloc(&c->d_red, c->red_len * sizeof(double), "reduction");
-    dmalloc(&c->d_small, static_cast<size_t>(R) * 8 * (c->restart + 2) * (c->restart + 2) * sizeof(double),
+    dmalloc(&c->d_small,
+            static_cast<size_t>(R) * (2 * (c->restart + 2) * (c->restart + 4) + 1200) * sizeof(double),
             "hessenberg");
     c->workspace_bytes = static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16 + 4 * vbytes +
                          static_cast<size_t>(c->restart + 2) * N * R * c->elt + 4 * vbytes;
+    if (c->prec != HBF_PREC_NONE) superleaf_entries(c.get());
     factor_leaves(c.get(), s);
     // release the host copies of the factors
     fill_stats(P, &c->stats, c->elt);
@@ -554,6 +682,47 @@ hbf_status hbf_precond_apply(hbf_ctx* c, const void* r, void* z, int32_t nrhs, h
   if (st != HBF_OK) return st;
   if (launch_to_external(c->d_vout, v128, z, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
   return HBF_OK;
+}
+
+hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
+  if (!c || !key) return fail(HBF_EINVAL, "hbf_tune: NULL argument");
+  const std::string k(key);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(HBF_EHIP, "hipSetDevice");
+  if (k == "prog_levels") {
+    if (value < 0 || value > 12) return fail(HBF_EINVAL, "hbf_tune: prog_levels out of range");
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    build_sweeps(c->P, c->S, static_cast<int>(value));
+    dfree(c->d_steps);
+    c->d_steps = nullptr;
+    try {
+      dmalloc(&c->d_steps, std::max<size_t>(c->S.steps.size(), 1) * sizeof(int32_t), "steps");
+    } catch (...) {
+      return fail(HBF_ENOMEM, "hbf_tune: out of device memory");
+    }
+    if (!c->S.steps.empty() &&
+        hipMemcpy(c->d_steps, c->S.steps.data(), c->S.steps.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return fail(HBF_EHIP, "hbf_tune: upload");
+    return HBF_OK;
+  }
+  if (k == "r1_kernel") { c->r1_kernel = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "prog_pipe") { c->prog_pipe = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "pipe_max_r") {
+    if (value < 0 || value > 1024) return fail(HBF_EINVAL, "hbf_tune: pipe_max_r out of range");
+    c->pipe_max_r = static_cast<int>(value);
+    free_graphs(c);
+    return HBF_OK;
+  }
+  if (k == "wave_units") { c->wave_units = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "use_graphs") { c->use_graphs = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "r1_max_blocks") {
+    if (value < 1 || value > (1 << 20)) return fail(HBF_EINVAL, "hbf_tune: r1_max_blocks out of range");
+    c->r1_max_blocks = static_cast<int>(value);
+    free_graphs(c);
+    return HBF_OK;
+  }
+  return fail(HBF_EINVAL, "hbf_tune: unknown key " + k);
 }
 
 hbf_status hbf_stats(const hbf_ctx* c, hbf_stats_t* out) {

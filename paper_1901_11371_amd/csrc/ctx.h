@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "hbf_internal.h"
@@ -20,6 +22,10 @@ struct hbf_ctx {
   int64_t n = 0;
   int elt = 8;                 // bytes per factor entry
   bool wave_units = true;      // one wave per group for one- or two-RHS launches
+  bool r1_kernel = false;      // register-streaming kernel for one-RHS launches (LDS atomics)
+  bool prog_pipe = true;       // pipelined wave teams in the sweep programs
+  int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
+  int r1_max_blocks = 2048;    // persistent grid size of that kernel
 
   // device memory
   void* d_fac = nullptr;       // factors + leaf inverses (storage dtype)
@@ -33,6 +39,9 @@ struct hbf_ctx {
   void* d_vout = nullptr;
   void* d_u = nullptr;         // preconditioner work
   void* d_t = nullptr;
+  void* d_pz = nullptr;        // preconditioner output of the captured graphs
+  bool use_graphs = true;      // replay the preconditioner sweeps from captured HIP graphs
+  std::map<std::pair<int, int>, hipGraphExec_t> pc_graphs;  // (nrhs, adjoint) -> graph
   hbf::cd* d_diag64 = nullptr; // FP64 diagonal leaf blocks (with z), column-major
   int* d_flag = nullptr;
   // solver workspace
@@ -44,6 +53,7 @@ struct hbf_ctx {
   size_t red_len = 0;
 
   std::vector<hbf::cd> diag_noz;  // host FP64 leaf blocks without z (for set_impedance)
+  std::vector<hbf::cd> sl_noz;    // host FP64 super-leaf blocks without z (row-major)
   hbf_stats_t stats{};
   double build_seconds = 0;
   size_t workspace_bytes = 0;

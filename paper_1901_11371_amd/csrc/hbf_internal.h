@@ -72,6 +72,7 @@ struct Launch {
   int32_t out_leaf;    // 1 if the launch writes rows of the external vector (uses alpha/beta)
   int32_t kind;        // 0 butterfly/dense, 1 leaf solve
   int32_t prog = 0;    // 1: a sequential program over steps [first, first+count) of the step table
+  int32_t force_fwd = 0;  // 1: apply the units in forward mode even in an adjoint schedule
 };
 
 // Per-butterfly-block bookkeeping.
@@ -105,9 +106,12 @@ struct Plan {
   // dense units: diag_unit[b] (A_bb), l0_unit[pair at level V] (lower and upper)
   std::vector<int32_t> diag_unit;
   std::vector<int32_t> l0_lower_unit, l0_upper_unit;  // per pair of the last level
-  // leaf-solve units (matrices filled on the device; host holds only the layout)
-  std::vector<int32_t> leaf_fwd_unit, leaf_bwd_unit;
-  int64_t leaf_fac_begin = 0;     // first complex entry of the leaf-inverse region
+  // super-leaf solve units: super-leaf S of 2^sl leaves owns units
+  // [sl_*[S], sl_*[S] + 2^sl), one row block per leaf; matrices are filled by
+  // the leaf factorisation (on the device, or on the host for the checks)
+  int sl = 2;
+  std::vector<int32_t> sl_fwd, sl_bwd, sl_adj_fwd, sl_adj_bwd;
+  int64_t leaf_fac_begin = 0;     // first complex entry of the super-leaf region
   int64_t leaf_fac_len = 0;
 
   // matvec schedules (forward and adjoint): launches over group tables

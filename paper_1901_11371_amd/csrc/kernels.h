@@ -43,6 +43,21 @@ constexpr int kWaveOutPerThread = 4;
 hipError_t launch_stage_c64(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s);
 hipError_t launch_stage_c128(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s);
 hipError_t launch_stage_c64_hi(const StageArgs& a, int ngroups, bool adjoint, size_t lds, hipStream_t s);
+// Software-pipelined wave teams (stage_pipe.hip): stage launches over
+// ngroups groups x nchunks RHS chunks, and sweep programs.
+int pipe_team_lds(int elt_acc, int elt_fac);
+hipError_t launch_pipe_c64(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s);
+hipError_t launch_pipe_c128(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s);
+hipError_t launch_pipe_c64_hi(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks,
+                              hipStream_t s);
+hipError_t launch_prog_pipe_c64(const StageArgs& a, const int32_t* steps, int s0, int s1, bool adjoint,
+                                hipStream_t s);
+hipError_t launch_prog_pipe_c128(const StageArgs& a, const int32_t* steps, int s0, int s1, bool adjoint,
+                                 hipStream_t s);
+// One-RHS variant: persistent waves, matrices streamed straight into registers.
+hipError_t launch_stage_r1_c64(const StageArgs& a, int ngroups, bool adjoint, int max_blocks, hipStream_t s);
+hipError_t launch_stage_r1_c128(const StageArgs& a, int ngroups, bool adjoint, int max_blocks, hipStream_t s);
+hipError_t launch_stage_r1_c64_hi(const StageArgs& a, int ngroups, bool adjoint, int max_blocks, hipStream_t s);
 // Wave-per-group variant (4 groups per workgroup, wave_lds bytes of LDS each).
 hipError_t launch_stage_wave_c64(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
 hipError_t launch_stage_wave_c128(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
@@ -59,12 +74,17 @@ hipError_t launch_program_c128(const StageArgs& a, const int32_t* steps, int s0,
 hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, int64_t n, int R, hipStream_t s);
 hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c128, int64_t n, int R, hipStream_t s);
 
-// Leaf factorisation in FP64 of leaves [b0, b0+nb): D (n0 x n0 blocks,
-// column-major, complex double) -> inverses written to out (storage dtype) at
-// out_fwd_off + b*stride (and out_bwd_off + b*stride for the second matrix of
-// the point-wise reading).  work holds nb * 2 n0^2 complex doubles.
-hipError_t launch_leaf_factor(const cd* D, int64_t b0, int64_t nb, int n0, int mode, double sre, double sim,
-                              void* out, int out_c128, int64_t out_fwd_off, int64_t out_bwd_off,
-                              int64_t stride, int* flag, cd* work, hipStream_t s);
+// Super-leaf factorisation in FP64 of super-leaves [S0, S0+nb): A holds their
+// exact diagonal blocks (row-major ns x ns each, batch-local); the inverses of
+// the lower and upper blocks of L~ / U~ are written as four row-block unit
+// sets at base[set] + S * per_superleaf (complex entries).  work holds
+// nb * 3 ns^2 complex doubles.
+struct SuperleafOut {
+  int64_t base[4];
+  int64_t per_superleaf;
+};
+hipError_t launch_superleaf_factor(const cd* A, int64_t S0, int64_t nb, int ns, int n0, int mode, double sre,
+                                  double sim, void* fac, int fac_c128, SuperleafOut so, int* flag, cd* work,
+                                  hipStream_t s);
 
 }  // namespace hbf

@@ -687,34 +687,54 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
     P.scale = 1.0 / P.self_entry(ib);
   }
 
-  // leaf-solve units: matrices live in a region after the factors and are
-  // filled by the leaf factorisation (forward and backward share it in the
-  // block reading)
+  // Super-leaf solve units.  The diagonal tree is cut at super-leaves of
+  // 2^sl leaves; inside one, the block substitution of Algorithms 3 / 4 is
+  // replaced by the inverse of that diagonal block of L~ (or U~), formed in
+  // FP64 from the exact entries and stored as one row block per leaf (a unit
+  // reading the super-leaf's input rows it depends on).  Four sets: forward
+  // (L inverse), backward (U inverse), and the conjugate transposes of the U
+  // and L inverses for the adjoint sweeps (those are applied in forward mode).
+  // Matrices live in a region after the factors and are filled by the leaf
+  // factorisation.
   const hbf_prec prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
-  P.leaf_fwd_unit.clear();
-  P.leaf_bwd_unit.clear();
+  P.sl = std::min(2, P.V);
+  const int s_leaves = 1 << P.sl;
+  const int64_t ns = static_cast<int64_t>(leaf) << P.sl;
+  const int64_t nsl = P.n / ns;
+  for (auto* v : {&P.sl_fwd, &P.sl_bwd, &P.sl_adj_fwd, &P.sl_adj_bwd}) v->clear();
   P.leaf_fac_begin = static_cast<int64_t>(P.fac.size());
   P.leaf_fac_len = 0;
   if (prec != HBF_PREC_NONE) {
-    const int nmat = (prec == HBF_PREC_PAPER_TRI) ? 2 : 1;
-    const int64_t sz = static_cast<int64_t>(leaf) * leaf;
-    P.leaf_fac_len = nmat * nl * ((sz + 1) & ~int64_t(1));
-    for (int64_t b = 0; b < nl; ++b) {
-      Unit u = blank_unit(UNIT_DENSE);
-      u.in_buf = BUF_Y;
-      u.out_buf = BUF_X;
-      u.in_off[0] = u.out_off[0] = static_cast<int32_t>(b * leaf);
-      u.in_len[0] = u.out_len[0] = static_cast<int16_t>(leaf);
-      u.mat_len = static_cast<int32_t>((sz + 1) & ~int64_t(1));
-      u.mat = P.leaf_fac_begin + b * u.mat_len;
-      u.perm = 0;
-      P.units.push_back(u);
-      P.leaf_fwd_unit.push_back(static_cast<int32_t>(P.units.size() - 1));
-      if (nmat == 2) u.mat = P.leaf_fac_begin + (nl + b) * u.mat_len;
-      P.units.push_back(u);
-      P.leaf_bwd_unit.push_back(static_cast<int32_t>(P.units.size() - 1));
+    int64_t off = P.leaf_fac_begin;
+    const int64_t b2 = static_cast<int64_t>(leaf) * leaf;
+    // set 0: lower-shaped forward, 1: upper-shaped backward, 2: lower-shaped
+    // adjoint-forward, 3: upper-shaped adjoint-backward
+    for (int set = 0; set < 4; ++set) {
+      std::vector<int32_t>& dst = set == 0 ? P.sl_fwd : set == 1 ? P.sl_bwd : set == 2 ? P.sl_adj_fwd : P.sl_adj_bwd;
+      const bool lower_shape = (set == 0 || set == 2);
+      for (int64_t S = 0; S < nsl; ++S) {
+        dst.push_back(static_cast<int32_t>(P.units.size()));
+        for (int i = 0; i < s_leaves; ++i) {
+          Unit u = blank_unit(UNIT_DENSE);
+          const int c0 = lower_shape ? 0 : i;                 // first leaf column of the row block
+          const int c1 = lower_shape ? i + 1 : s_leaves;      // end leaf column
+          u.in_buf = (set < 2) ? BUF_Y : BUF_X;
+          u.out_buf = (set < 2) ? BUF_X : BUF_Y;
+          u.in_off[0] = static_cast<int32_t>(S * ns + static_cast<int64_t>(c0) * leaf);
+          u.in_len[0] = static_cast<int16_t>((c1 - c0) * leaf);
+          u.out_off[0] = static_cast<int32_t>(S * ns + static_cast<int64_t>(i) * leaf);
+          u.out_len[0] = static_cast<int16_t>(leaf);
+          u.mat_len = static_cast<int32_t>(b2 * (c1 - c0));
+          u.mat = off;
+          off += u.mat_len;
+          u.perm = 0;
+          P.units.push_back(u);
+        }
+      }
     }
+    P.leaf_fac_len = off - P.leaf_fac_begin;
   }
+  (void)ns;
 
   // ---- matvec schedules ----
   int Dmax = 0;

@@ -6,6 +6,9 @@
 #include <cstring>
 #include <memory>
 #include <stdexcept>
+#include <atomic>
+#include <mutex>
+#include <thread>
 
 #include "hbf_internal.h"
 #include "schedule.h"
@@ -33,7 +36,7 @@ struct SweepGen {
   const Plan& P;
   const std::vector<int>& level_base;
   bool lower_dir, adjoint;
-  const std::vector<int32_t>& leaf_units;
+  const std::vector<int32_t>& leaf_units;   // first unit of each super-leaf
   std::vector<Launch>& out;
   std::vector<int32_t>& steps;
   int prog_levels;
@@ -48,11 +51,11 @@ struct SweepGen {
     }
   }
   // emit one ordered step (into a program when `prog` is non-null)
-  void emit(int32_t u0, int32_t u1, int acc, int kind, Launch* prog) {
+  void emit(int32_t u0, int32_t u1, int acc, int kind, Launch* prog, int force_fwd = 0) {
     if (prog) {
       steps.push_back(u0);
       steps.push_back(u1);
-      steps.push_back(acc);
+      steps.push_back(acc | (force_fwd << 1));
       prog->count += 1;
       bound(*prog, u0, u1);
       return;
@@ -65,6 +68,7 @@ struct SweepGen {
     l.out_leaf = acc;
     l.kind = kind;
     l.prog = 0;
+    l.force_fwd = force_fwd;
     bound(l, u0, u1);
     out.push_back(l);
   }
@@ -82,8 +86,10 @@ struct SweepGen {
       out.push_back(l);
       return;
     }
-    if (dd == P.V) {
-      emit(leaf_units[idx], leaf_units[idx] + 1, 0, 1, prog);
+    if (dd == P.V - P.sl) {
+      // super-leaf solve: one row-block unit per leaf, all independent; the
+      // adjoint sweeps use the stored conjugate-transposed sets in forward mode
+      emit(leaf_units[idx], leaf_units[idx] + (1 << P.sl), 0, 1, prog, adjoint ? 1 : 0);
       return;
     }
     const int64_t first = lower_dir ? 2 * idx : 2 * idx + 1;
@@ -122,18 +128,30 @@ void build_sweeps(const Plan& P, Sweeps& S, int prog_levels) {
   S.adj_bwd.clear();
   S.steps.clear();
   S.prog_levels = prog_levels;
-  if (P.leaf_fwd_unit.empty()) return;
-  // P^{-1}: lower sweep with the forward leaf solves, upper with the backward ones.
-  // P^{-H}: the lower sweep solves with the backward leaf matrices conjugate-
-  // transposed, the upper sweep with the forward ones.
-  SweepGen g1{P, level_base, true, false, P.leaf_fwd_unit, S.fwd, S.steps, prog_levels};
+  if (P.sl_fwd.empty()) return;
+  // P^{-1}: lower sweep with the L~ super-leaf inverses, upper with the U~ ones.
+  // P^{-H}: lower sweep with (U~ inverse)^H, upper with (L~ inverse)^H.
+  SweepGen g1{P, level_base, true, false, P.sl_fwd, S.fwd, S.steps, prog_levels};
   g1.rec(0, 0, nullptr);
-  SweepGen g2{P, level_base, false, false, P.leaf_bwd_unit, S.bwd, S.steps, prog_levels};
+  SweepGen g2{P, level_base, false, false, P.sl_bwd, S.bwd, S.steps, prog_levels};
   g2.rec(0, 0, nullptr);
-  SweepGen g3{P, level_base, true, true, P.leaf_bwd_unit, S.adj_fwd, S.steps, prog_levels};
+  SweepGen g3{P, level_base, true, true, P.sl_adj_fwd, S.adj_fwd, S.steps, prog_levels};
   g3.rec(0, 0, nullptr);
-  SweepGen g4{P, level_base, false, true, P.leaf_fwd_unit, S.adj_bwd, S.steps, prog_levels};
+  SweepGen g4{P, level_base, false, true, P.sl_adj_bwd, S.adj_bwd, S.steps, prog_levels};
   g4.rec(0, 0, nullptr);
+  // the block reading's middle vector s = D t uses the diagonal leaf units
+  const int64_t nl = P.n / P.n0;
+  Launch d;
+  d.direct = 1;
+  d.first = P.diag_unit.empty() ? 0 : P.diag_unit[0];
+  d.count = static_cast<int32_t>(nl);
+  d.max_src = d.max_dst = P.n0;
+  d.max_mat = P.n0 * P.n0;
+  d.out_leaf = 0;
+  d.kind = 0;
+  d.prog = 0;
+  d.force_fwd = 0;
+  S.diag = {d};
 }
 
 // ---------------------------------------------------------------------------
@@ -250,14 +268,17 @@ void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cpl
         l.direct = 1;
         l.first = (*steps)[3 * st];
         l.count = (*steps)[3 * st + 1] - (*steps)[3 * st];
-        l.out_leaf = (*steps)[3 * st + 2];
+        l.out_leaf = (*steps)[3 * st + 2] & 1;
+        l.force_fwd = ((*steps)[3 * st + 2] >> 1) & 1;
         expanded.push_back(l);
       }
     } else {
       expanded.push_back(L0);
     }
   }
+  const bool adj_all = adj;
   for (const Launch& L : expanded) {
+    const bool adj = adj_all && !L.force_fwd;
     for (int g = L.first; g < L.first + L.count; ++g) {
       std::vector<int32_t> us;
       if (L.direct) {
@@ -336,38 +357,86 @@ static void invert_dense(std::vector<cplx>& A, int n) {
   A.swap(I);
 }
 
-void host_leaf_factor(Plan& P, hbf_prec prec) {
-  if (P.leaf_fwd_unit.empty()) return;
-  P.fac.resize(P.leaf_fac_begin + P.leaf_fac_len, cplx(0.0));
+// Fill the four super-leaf sets from the inverses Linv (of the lower block)
+// and Uinv (of the upper block) of super-leaf S (both row-major ns x ns).
+void store_superleaf(Plan& P, int64_t S, const std::vector<cplx>& Linv, const std::vector<cplx>& Uinv) {
   const int n0 = P.n0;
-  const int64_t nl = P.n / n0;
-  for (int64_t b = 0; b < nl; ++b) {
-    const Unit& du = P.units[P.diag_unit[b]];
-    std::vector<cplx> A(static_cast<size_t>(n0) * n0);  // row-major copy of A_bb
-    for (int t = 0; t < n0; ++t)
-      for (int i = 0; i < n0; ++i) A[static_cast<size_t>(i) * n0 + t] = P.fac[du.mat + static_cast<size_t>(t) * n0 + i];
-    auto store = [&](const std::vector<cplx>& Minv, const Unit& u) {
-      for (int t = 0; t < n0; ++t)
-        for (int i = 0; i < n0; ++i) P.fac[u.mat + static_cast<size_t>(t) * n0 + i] = Minv[static_cast<size_t>(i) * n0 + t];
-    };
-    if (prec == HBF_PREC_BLOCK_LU) {
-      invert_dense(A, n0);
-      store(A, P.units[P.leaf_fwd_unit[b]]);
-    } else {
-      std::vector<cplx> Lm(static_cast<size_t>(n0) * n0, cplx(0.0)), Um(static_cast<size_t>(n0) * n0, cplx(0.0));
-      for (int i = 0; i < n0; ++i)
-        for (int j = 0; j < n0; ++j) {
-          const cplx a = A[static_cast<size_t>(i) * n0 + j];
-          if (i > j) Lm[static_cast<size_t>(i) * n0 + j] = P.scale * a;
-          if (i == j) Lm[static_cast<size_t>(i) * n0 + j] = 1.0;
-          if (i <= j) Um[static_cast<size_t>(i) * n0 + j] = a;
+  const int s_leaves = 1 << P.sl;
+  const int64_t ns = static_cast<int64_t>(n0) << P.sl;
+  for (int set = 0; set < 4; ++set) {
+    const std::vector<int32_t>& first = set == 0 ? P.sl_fwd : set == 1 ? P.sl_bwd : set == 2 ? P.sl_adj_fwd : P.sl_adj_bwd;
+    for (int i = 0; i < s_leaves; ++i) {
+      const Unit& u = P.units[first[S] + i];
+      const int c0 = (u.in_off[0] - static_cast<int32_t>(S * ns));
+      const int w = u.in_len[0];
+      for (int c = 0; c < w; ++c)
+        for (int r = 0; r < n0; ++r) {
+          const int64_t gr = static_cast<int64_t>(i) * n0 + r, gc = c0 + c;
+          cplx v;
+          if (set == 0) v = Linv[gr * ns + gc];
+          else if (set == 1) v = Uinv[gr * ns + gc];
+          else if (set == 2) v = std::conj(Uinv[gc * ns + gr]);
+          else v = std::conj(Linv[gc * ns + gr]);
+          P.fac[u.mat + static_cast<int64_t>(c) * n0 + r] = v;
         }
-      invert_dense(Lm, n0);
-      invert_dense(Um, n0);
-      store(Lm, P.units[P.leaf_fwd_unit[b]]);
-      store(Um, P.units[P.leaf_bwd_unit[b]]);
     }
   }
+}
+
+// The lower and upper super-leaf blocks of L~ / U~ (row-major ns x ns) from
+// the exact entries A_SS (row-major): block reading D + A_low, D + A_up;
+// point-wise reading I + a * strict_lower(A), upper(A).
+void superleaf_blocks(const Plan& P, const std::vector<cplx>& A, hbf_prec prec, std::vector<cplx>& Lm,
+                      std::vector<cplx>& Um) {
+  const int64_t ns = static_cast<int64_t>(P.n0) << P.sl;
+  Lm.assign(ns * ns, cplx(0.0));
+  Um.assign(ns * ns, cplx(0.0));
+  for (int64_t i = 0; i < ns; ++i)
+    for (int64_t j = 0; j < ns; ++j) {
+      const cplx a = A[i * ns + j];
+      if (prec == HBF_PREC_BLOCK_LU) {
+        const int64_t bi = i / P.n0, bj = j / P.n0;
+        if (bi >= bj) Lm[i * ns + j] = a;
+        if (bi <= bj) Um[i * ns + j] = a;
+      } else {
+        if (i > j) Lm[i * ns + j] = P.scale * a;
+        if (i == j) Lm[i * ns + j] = 1.0;
+        if (i <= j) Um[i * ns + j] = a;
+      }
+    }
+}
+
+void host_leaf_factor(Plan& P, hbf_prec prec) {
+  if (P.sl_fwd.empty()) return;
+  P.fac.resize(P.leaf_fac_begin + P.leaf_fac_len, cplx(0.0));
+  const int64_t ns = static_cast<int64_t>(P.n0) << P.sl;
+  const int64_t nsl = P.n / ns;
+  std::vector<std::thread> th;
+  std::atomic<int64_t> next(0);
+  std::exception_ptr err = nullptr;
+  std::mutex mu;
+  const int T = std::max(1, std::min<int>(8, static_cast<int>(std::thread::hardware_concurrency())));
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&]() {
+      try {
+        for (;;) {
+          const int64_t S = next.fetch_add(1);
+          if (S >= nsl) return;
+          std::vector<cplx> A(ns * ns), Lm, Um;
+          for (int64_t i = 0; i < ns; ++i)
+            for (int64_t j = 0; j < ns; ++j) A[i * ns + j] = P.entry(S * ns + i, S * ns + j);
+          superleaf_blocks(P, A, prec, Lm, Um);
+          invert_dense(Lm, static_cast<int>(ns));
+          invert_dense(Um, static_cast<int>(ns));
+          store_superleaf(P, S, Lm, Um);
+        }
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!err) err = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
 }
 
 }  // namespace hbf
@@ -452,10 +521,12 @@ hbf_status hbf_plan_precond(const hbf_plan* plan, const double* rin, double* zou
     const cplx a = paper ? P.scale : cplx(1.0);
     if (!adjoint) {
       exec_host(P, S.fwd, false, t.data(), u.data(), arena.data(), nrhs, -a, &S.steps);
+      if (!paper) exec_host(P, S.diag, false, t.data(), u.data(), arena.data(), nrhs, 0.0);  // u = D t
       cplx* mid = paper ? t.data() : u.data();
       exec_host(P, S.bwd, false, z.data(), mid, arena.data(), nrhs, -1.0, &S.steps);
     } else {
       exec_host(P, S.adj_fwd, true, u.data(), t.data(), arena.data(), nrhs, -1.0, &S.steps);
+      if (!paper) exec_host(P, S.diag, true, u.data(), t.data(), arena.data(), nrhs, 0.0);  // u = D^H t
       cplx* mid = paper ? t.data() : u.data();
       exec_host(P, S.adj_bwd, true, mid, z.data(), arena.data(), nrhs, -std::conj(a), &S.steps);
     }

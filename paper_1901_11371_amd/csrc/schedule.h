@@ -11,7 +11,8 @@ namespace hbf {
 struct Sweeps {
   std::vector<Launch> fwd, bwd;          // P^{-1}: lower then upper substitution
   std::vector<Launch> adj_fwd, adj_bwd;  // P^{-H}
-  std::vector<int32_t> steps;            // program steps: (first unit, end unit, accumulate)
+  std::vector<Launch> diag;              // s = D t (block reading, between the sweeps)
+  std::vector<int32_t> steps;            // program steps: (first unit, end unit, flags: 1 accumulate, 2 forward mode)
   int prog_levels = 6;                   // subtrees of <= 2^prog_levels leaves run as one program
 };
 
@@ -25,6 +26,8 @@ void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cpl
                cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps = nullptr);
 
 void host_leaf_factor(Plan& P, hbf_prec prec);
+void superleaf_blocks(const Plan& P, const std::vector<cplx>& A, hbf_prec prec, std::vector<cplx>& Lm,
+                      std::vector<cplx>& Um);
 
 const char* last_error();
 

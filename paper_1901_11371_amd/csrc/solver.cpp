@@ -45,7 +45,7 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
   if (opts) o = *opts;
   const double tol = o.tol > 0 ? o.tol : 1e-6;
   const int m = (o.restart > 0) ? std::min(o.restart, c->restart) : c->restart;
-  if (m < 1 || m > 63) { set_error(std::string(name) + ": restart must be in [1, 63]"); return HBF_EINVAL; }
+  if (m < 1 || m > 255) { set_error(std::string(name) + ": restart must be in [1, 255]"); return HBF_EINVAL; }
   const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
   const int max_refine = o.max_refine > 0 ? o.max_refine : 10;
   const bool inner128 = c->dtype == HBF_C128;
@@ -72,9 +72,9 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
     double* small = c->d_small;
     const int64_t per = gm_small_per_rhs(m);
     cd* h = reinterpret_cast<cd*>(small + per * R);
-    cd* nrm2 = h + 64 * R;
+    cd* nrm2 = h + 256 * R;
     cd* ycoef = nrm2 + R;
-    double* inv = reinterpret_cast<double*>(ycoef + 64 * R);
+    double* inv = reinterpret_cast<double*>(ycoef + 256 * R);
     double* resid = inv + R;
     double* target = resid + R;
     int* active = reinterpret_cast<int*>(target + R);
@@ -138,7 +138,9 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
         chk(precond_internal(c, Vj(j), z, R, adjoint, s), "preconditioner");
         chk(matvec_internal(c, z, w, R, inner128, adjoint, s), "matvec");
         for (int pass = 0; pass < 2; ++pass) {
-          chk(gm_dots(inner128, V, vstride, j + 1, w, N, R, partial, plen, h, s), "dots");
+          for (int i0 = 0; i0 <= j; i0 += 32)  // dot products in chunks of up to 32 basis vectors
+            chk(gm_dots(inner128, Vj(i0), vstride, std::min(32, j + 1 - i0), w, N, R, partial, plen, h + i0 * R, s),
+                "dots");
           chk(gm_sub_combo(inner128, V, vstride, j + 1, h, w, N, R, s), "orthogonalise");
           chk(gm_h_accum(small, m, R, j, h, s), "hessenberg");
         }

@@ -325,13 +325,19 @@ __global__ void __launch_bounds__(kProgThreads) k_program(StageArgs a, const int
   const int chunk = blockIdx.x;
   const double are = a.alpha_re, aim = a.alpha_im;
   for (int st = s0; st < s1; ++st) {
-    const int u0 = steps[3 * st], u1 = steps[3 * st + 1], acc = steps[3 * st + 2];
+    const int u0 = steps[3 * st], u1 = steps[3 * st + 1], flags = steps[3 * st + 2];
+    const int acc = flags & 1;
+    const bool fwd_mode = (flags >> 1) & 1;
     StageArgs b = a;
     b.acc = acc;
     b.alpha_re = acc ? are : 0.0;
     b.alpha_im = acc ? aim : 0.0;
-    for (int u = u0 + wave; u < u1; u += kProgWaves)
-      process_group<F, V, A, ADJ, 64, kProgOutPerThread>(b, u, u + 1, true, chunk, lane, my, WaveSync{});
+    for (int u = u0 + wave; u < u1; u += kProgWaves) {
+      if (ADJ && fwd_mode)
+        process_group<F, V, A, false, 64, kProgOutPerThread>(b, u, u + 1, true, chunk, lane, my, WaveSync{});
+      else
+        process_group<F, V, A, ADJ, 64, kProgOutPerThread>(b, u, u + 1, true, chunk, lane, my, WaveSync{});
+    }
     __threadfence_block();
     __syncthreads();
   }
@@ -404,21 +410,24 @@ __device__ __forceinline__ cd cdiv(cd a, cd b) {
 }
 __device__ __forceinline__ cd cmul(cd a, cd b) { return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
-// Gauss-Jordan on W = [M | I] (n x 2n, row-major in global scratch); result
-// inverse written to out (column-major n x n).
-template <class F>
-__device__ void gauss_jordan(cd* W, int n, bool pivot, cx<F>* out, int* flag) {
+// Gauss-Jordan elimination on W = [M | I] (n x 2n, row-major, global
+// scratch), in place: on return W[:, n:2n] = M^{-1}.  Partial pivoting on
+// request; a zero pivot sets *flag.
+__device__ void gauss_jordan_inplace(cd* W, int n, bool pivot, int* flag) {
   const int tid = threadIdx.x;
   const int w = 2 * n;
   __shared__ int s_piv;
   __shared__ double s_best[256];
   __shared__ int s_arg[256];
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
   for (int c = 0; c < n; ++c) {
     if (pivot) {
       double best = -1.0;
       int arg = c;
       for (int r = c + tid; r < n; r += blockDim.x) {
-        const cd v = W[r * w + c];
+        const cd v = W[static_cast<int64_t>(r) * w + c];
         const double m = v.x * v.x + v.y * v.y;
         if (m > best) { best = m; arg = r; }
       }
@@ -431,94 +440,113 @@ __device__ void gauss_jordan(cd* W, int n, bool pivot, cx<F>* out, int* flag) {
         for (int t = 0; t < static_cast<int>(blockDim.x); ++t)
           if (s_best[t] > b || (s_best[t] == b && s_arg[t] < ar)) { b = s_best[t]; ar = s_arg[t]; }
         s_piv = ar;
-        if (!(b > 0.0)) atomicExch(flag, 1);
       }
       __syncthreads();
       const int p = s_piv;
       if (p != c) {
         for (int j = tid; j < w; j += blockDim.x) {
-          const cd t = W[p * w + j];
-          W[p * w + j] = W[c * w + j];
-          W[c * w + j] = t;
+          const cd t = W[static_cast<int64_t>(p) * w + j];
+          W[static_cast<int64_t>(p) * w + j] = W[static_cast<int64_t>(c) * w + j];
+          W[static_cast<int64_t>(c) * w + j] = t;
         }
       }
       __syncthreads();
     }
-    const cd piv = W[c * w + c];
+    const cd piv = W[static_cast<int64_t>(c) * w + c];
     if (!(piv.x * piv.x + piv.y * piv.y > 0.0)) {
-      if (tid == 0) atomicExch(flag, 1);
-      return;
+      if (tid == 0) {
+        atomicExch(flag, 1);
+        s_bad = 1;
+      }
     }
     __syncthreads();
-    // scale pivot row
-    for (int j = tid; j < w; j += blockDim.x) W[c * w + j] = cdiv(W[c * w + j], piv);
+    if (s_bad) return;
+    for (int j = tid; j < w; j += blockDim.x) W[static_cast<int64_t>(c) * w + j] = cdiv(W[static_cast<int64_t>(c) * w + j], piv);
     __syncthreads();
-    // eliminate column c from the other rows
     for (int e = tid; e < n * w; e += blockDim.x) {
       const int r = e / w, j = e - r * w;
       if (r == c || j == c) continue;
-      const cd f = W[r * w + c];
-      const cd v = W[c * w + j];
+      const cd f = W[static_cast<int64_t>(r) * w + c];
+      if (f.x == 0.0 && f.y == 0.0) continue;
+      const cd v = W[static_cast<int64_t>(c) * w + j];
       const cd m = cmul(f, v);
-      W[r * w + j] = cd{W[r * w + j].x - m.x, W[r * w + j].y - m.y};
+      W[static_cast<int64_t>(r) * w + j] = cd{W[static_cast<int64_t>(r) * w + j].x - m.x, W[static_cast<int64_t>(r) * w + j].y - m.y};
     }
     __syncthreads();
     for (int r = tid; r < n; r += blockDim.x)
-      if (r != c) W[r * w + c] = cd{0.0, 0.0};
+      if (r != c) W[static_cast<int64_t>(r) * w + c] = cd{0.0, 0.0};
     __syncthreads();
-  }
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int t = e / n, i = e - t * n;  // column-major (i, t)
-    const cd v = W[i * w + n + t];
-    out[e] = cx<F>{static_cast<F>(v.x), static_cast<F>(v.y)};
   }
 }
 
+// Super-leaf factorisation in FP64: one workgroup per super-leaf.  A holds
+// the exact entries of the super-leaf's diagonal block (row-major ns x ns).
+// The lower and upper blocks of L~ / U~ are inverted by Gauss-Jordan (with
+// partial pivoting in the block reading, where they have full n0 x n0
+// diagonal blocks) and written as the four row-block unit sets.
 template <class F>
-__global__ void k_leaf_factor(const cd* D, int64_t b0, int n0, int mode, double sre, double sim, cx<F>* out,
-                              int64_t fwd_off, int64_t bwd_off, int64_t stride, int* flag, cd* work) {
-  const int64_t b = b0 + blockIdx.x;
-  const cd* Db = D + b * n0 * n0;  // column-major
-  cd* W = work + static_cast<int64_t>(blockIdx.x) * n0 * 2 * n0;
-  const int w = 2 * n0;
+__global__ void __launch_bounds__(256) k_superleaf_factor(const cd* A, int64_t S0, int ns, int n0, int mode,
+                                                          double sre, double sim, cx<F>* fac, SuperleafOut so,
+                                                          int* flag, cd* work) {
+  const int64_t S = S0 + blockIdx.x;
+  const cd* As = A + static_cast<int64_t>(blockIdx.x) * ns * ns;
+  cd* W = work + static_cast<int64_t>(blockIdx.x) * ns * 2 * ns;
+  cd* Linv = work + static_cast<int64_t>(gridDim.x) * ns * 2 * ns + static_cast<int64_t>(blockIdx.x) * ns * ns;
+  const int w = 2 * ns;
   const int tid = threadIdx.x;
-  if (mode == 0) {
-    for (int e = tid; e < n0 * w; e += blockDim.x) {
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool lower = pass == 0;
+    for (int e = tid; e < ns * w; e += blockDim.x) {
       const int r = e / w, j = e - r * w;
-      W[e] = (j < n0) ? Db[j * n0 + r] : cd{(j - n0 == r) ? 1.0 : 0.0, 0.0};
+      cd v{0.0, 0.0};
+      if (j < ns) {
+        const cd a = As[static_cast<int64_t>(r) * ns + j];
+        if (mode == 0) {
+          const int br = r / n0, bj = j / n0;
+          if (lower ? (br >= bj) : (br <= bj)) v = a;
+        } else if (lower) {
+          if (r > j) v = cmul(cd{sre, sim}, a);
+          else if (r == j) v = cd{1.0, 0.0};
+        } else if (r <= j) {
+          v = a;
+        }
+      } else {
+        v = cd{(j - ns == r) ? 1.0 : 0.0, 0.0};
+      }
+      W[e] = v;
     }
     __syncthreads();
-    gauss_jordan<F>(W, n0, true, out + fwd_off + b * stride, flag);
-    return;
-  }
-  // lower: I + a * strict_lower(D)
-  for (int e = tid; e < n0 * w; e += blockDim.x) {
-    const int r = e / w, j = e - r * w;
-    cd v{0.0, 0.0};
-    if (j < n0) {
-      if (r > j) v = cmul(cd{sre, sim}, Db[j * n0 + r]);
-      else if (r == j) v = cd{1.0, 0.0};
-    } else {
-      v = cd{(j - n0 == r) ? 1.0 : 0.0, 0.0};
+    gauss_jordan_inplace(W, ns, mode == 0, flag);
+    __syncthreads();
+    if (lower) {
+      for (int e = tid; e < ns * ns; e += blockDim.x) {
+        const int r = e / ns, c = e - r * ns;
+        Linv[e] = W[static_cast<int64_t>(r) * w + ns + c];
+      }
+      __syncthreads();
     }
-    W[e] = v;
   }
-  __syncthreads();
-  gauss_jordan<F>(W, n0, false, out + fwd_off + b * stride, flag);
-  __syncthreads();
-  // upper: triu(D)
-  for (int e = tid; e < n0 * w; e += blockDim.x) {
-    const int r = e / w, j = e - r * w;
-    cd v{0.0, 0.0};
-    if (j < n0) {
-      if (r <= j) v = Db[j * n0 + r];
-    } else {
-      v = cd{(j - n0 == r) ? 1.0 : 0.0, 0.0};
+  // W[:, ns:] holds Uinv, Linv the lower inverse; write the four sets
+  const int sl = ns / n0;
+  for (int set = 0; set < 4; ++set) {
+    const bool lower_shape = (set == 0 || set == 2);
+    int64_t off = so.base[set] + S * so.per_superleaf;
+    for (int i = 0; i < sl; ++i) {
+      const int c0 = lower_shape ? 0 : i * n0;
+      const int wid = lower_shape ? (i + 1) * n0 : (sl - i) * n0;
+      for (int e = tid; e < n0 * wid; e += blockDim.x) {
+        const int c = e / n0, r = e - c * n0;
+        const int gr = i * n0 + r, gc = c0 + c;
+        cd v;
+        if (set == 0) v = Linv[static_cast<int64_t>(gr) * ns + gc];
+        else if (set == 1) v = W[static_cast<int64_t>(gr) * w + ns + gc];
+        else if (set == 2) { v = W[static_cast<int64_t>(gc) * w + ns + gr]; v.y = -v.y; }
+        else { v = Linv[static_cast<int64_t>(gc) * ns + gr]; v.y = -v.y; }
+        fac[off + e] = cx<F>{static_cast<F>(v.x), static_cast<F>(v.y)};
+      }
+      off += static_cast<int64_t>(n0) * wid;
     }
-    W[e] = v;
   }
-  __syncthreads();
-  gauss_jordan<F>(W, n0, false, out + bwd_off + b * stride, flag);
 }
 
 unsigned blocks_for(int64_t n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
@@ -570,15 +598,15 @@ hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c1
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_factor(const cd* D, int64_t b0, int64_t nb, int n0, int mode, double sre, double sim,
-                              void* out, int out_c128, int64_t out_fwd_off, int64_t out_bwd_off, int64_t stride,
-                              int* flag, cd* work, hipStream_t s) {
-  if (out_c128)
-    hipLaunchKernelGGL((k_leaf_factor<double>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, D, b0, n0, mode,
-                       sre, sim, (cd*)out, out_fwd_off, out_bwd_off, stride, flag, work);
+hipError_t launch_superleaf_factor(const cd* A, int64_t S0, int64_t nb, int ns, int n0, int mode, double sre,
+                                  double sim, void* fac, int fac_c128, SuperleafOut so, int* flag, cd* work,
+                                  hipStream_t s) {
+  if (fac_c128)
+    hipLaunchKernelGGL((k_superleaf_factor<double>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, A, S0, ns, n0,
+                       mode, sre, sim, (cd*)fac, so, flag, work);
   else
-    hipLaunchKernelGGL((k_leaf_factor<float>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, D, b0, n0, mode,
-                       sre, sim, (cf*)out, out_fwd_off, out_bwd_off, stride, flag, work);
+    hipLaunchKernelGGL((k_superleaf_factor<float>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, s, A, S0, ns, n0,
+                       mode, sre, sim, (cf*)fac, so, flag, work);
   return hipGetLastError();
 }
 

@@ -186,6 +186,9 @@ class Context:
             mixed = self.dtype == "c64"
         return self._solve(self.lib.hbf_solve_adjoint, g, tol, restart, max_iters, max_refine, mixed, x0, inner_tol)
 
+    def tune(self, key, value):
+        check(self.lib, self.lib.hbf_tune(self.h, key.encode(), int(value)))
+
     def set_impedance(self, z):
         zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
         check(self.lib, self.lib.hbf_set_impedance(self.h, zz.ctypes.data_as(C.POINTER(C.c_double))))
