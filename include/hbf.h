@@ -116,6 +116,12 @@ typedef struct {
   int64_t bytes_workspace;       /* device workspace (skeleton arena, Krylov basis, ...) */
   double build_seconds;          /* host construction + upload time */
   double scale_re, scale_im;     /* a = 1 / A[i*, i*] */
+  /* Algorithmic bytes of one single-RHS application: every unit's matrices,
+   * permutations and 64-byte descriptor once, plus the input and output
+   * N-vectors in the context dtype.  Each further RHS adds 2 N-vectors. */
+  int64_t apply_bytes_matvec;    /* y = A x (Algorithm 2) */
+  int64_t apply_bytes_precond;   /* z = P^{-1} r (both sweeps, and s = D t in the block reading) */
+  int64_t launches_matvec;       /* kernel launches of one matvec */
 } hbf_stats_t;
 
 /* Build the H-IDBF of A = Z + diag(z) for the curve at wavenumber `kappa`
@@ -171,6 +177,8 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *                   stages (when pipe_max_r is 0),
  *   "r1_max_blocks" persistent grid size (workgroups) of the one-RHS kernels,
  *   "wave_units"    1 = one wave per unit for two-RHS stages,
+ *   "lane_split"    1 = in the pipelined kernels, up to 32 lanes share the
+ *                   dot product of one output of a unit with few outputs,
  *   "use_graphs"    1 = replay the preconditioner sweeps from HIP graphs.
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);

@@ -39,7 +39,8 @@ class Stats(C.Structure):
                 ("n_units", C.c_int64), ("max_rank", C.c_int32), ("mean_rank", C.c_double),
                 ("bytes_butterfly", C.c_int64), ("bytes_dense", C.c_int64), ("bytes_index", C.c_int64),
                 ("bytes_precond", C.c_int64), ("bytes_workspace", C.c_int64), ("build_seconds", C.c_double),
-                ("scale_re", C.c_double), ("scale_im", C.c_double)]
+                ("scale_re", C.c_double), ("scale_im", C.c_double), ("apply_bytes_matvec", C.c_int64),
+                ("apply_bytes_precond", C.c_int64), ("launches_matvec", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

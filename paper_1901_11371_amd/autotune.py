@@ -1,13 +1,16 @@
 """Autotuner for the execution parameters of an hbf context.
 
-It times the preconditioner application (the latency-bound sweeps) and the
-matvec for a given number of right-hand sides over the candidate values of
-each parameter exposed by ``hbf_tune`` and keeps the fastest:
+It times the applications one GMRES iteration makes (one preconditioner
+application and one matvec) for a given number of right-hand sides over the
+candidate values of the parameters exposed by ``hbf_tune`` and keeps the
+fastest:
 
 * ``prog_levels``: subtrees of at most 2^p leaves are swept inside one
-  workgroup program (deep subtrees: fewer launches, but a single workgroup
-  per RHS chunk streams their factors);
-* ``r1_max_blocks``: persistent grid size of the one-RHS stage kernel.
+  workgroup program (deep subtrees: fewer launches and cheap step
+  barriers, but one workgroup per RHS chunk streams their factors);
+* the stage kernel of the matvec and of the big sweep blocks: the
+  software-pipelined wave teams (``pipe_max_r`` >= nrhs), one unit per wave
+  (``wave_units``), or one unit per workgroup.
 
 Results are cached in a JSON table keyed by (N, nrhs, dtype, preconditioner)
 so later runs of the same shape apply them without timing.
@@ -20,6 +23,13 @@ import os
 import torch
 
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "autotune.json")
+
+# stage-kernel variants: name -> hbf_tune settings
+KERNELS = {
+    "pipe": lambda R: {"pipe_max_r": max(R, 1), "wave_units": 1},
+    "wave": lambda R: {"pipe_max_r": 0, "wave_units": 1},
+    "block": lambda R: {"pipe_max_r": 0, "wave_units": 0},
+}
 
 
 def _key(ctx, nrhs):
@@ -58,39 +68,47 @@ def apply(ctx, nrhs, path=DEFAULT_TABLE):
     return entry
 
 
-def autotune(ctx, nrhs=1, reps=3, prog_levels=(3, 4, 5, 6, 7, 8), r1_blocks=(512, 1024, 2048, 4096),
-             path=DEFAULT_TABLE, verbose=False):
+def autotune(ctx, nrhs=1, reps=2, prog_levels=(4, 5, 6, 7, 8), kernels=("pipe", "wave"), path=DEFAULT_TABLE,
+             verbose=False):
     """Time the candidates on `ctx` (an hbf.Context) and keep the best."""
     dt = torch.complex64 if ctx.dtype == "c64" else torch.complex128
-    x = torch.randn((nrhs, ctx.n), dtype=dt, device=ctx.device) if nrhs > 1 else \
-        torch.randn((ctx.n,), dtype=dt, device=ctx.device)
+    shape = (nrhs, ctx.n) if nrhs > 1 else (ctx.n,)
+    x = torch.randn(shape, dtype=dt, device=ctx.device)
     best = {}
     timings = {}
+
+    def say(msg):
+        if verbose:
+            print(f"[autotune] {msg}", flush=True)
+
     if ctx.prec != "none":
         res = {}
         for p in prog_levels:
             ctx.tune("prog_levels", p)
             res[p] = _time(lambda: ctx.precond(x), reps)
-            if verbose:
-                print(f"[autotune] prog_levels={p}: precond {res[p]:.3f} ms", flush=True)
+            say(f"prog_levels={p}: precond {res[p]:.3f} ms")
         p = min(res, key=res.get)
         best["prog_levels"] = p
         timings["precond_ms"] = res
         ctx.tune("prog_levels", p)
-    if nrhs == 1:
-        res = {}
-        for b in r1_blocks:
-            ctx.tune("r1_max_blocks", b)
-            res[b] = _time(lambda: ctx.matvec(x), reps * 3)
-            if verbose:
-                print(f"[autotune] r1_max_blocks={b}: matvec {res[b]:.3f} ms", flush=True)
-        b = min(res, key=res.get)
-        best["r1_max_blocks"] = b
-        timings["matvec_ms"] = res
-        ctx.tune("r1_max_blocks", b)
+    res = {}
+    for name in kernels:
+        for k, v in KERNELS[name](nrhs).items():
+            ctx.tune(k, v)
+        t = _time(lambda: ctx.matvec(x), reps)
+        if ctx.prec != "none":
+            t += _time(lambda: ctx.precond(x), reps)
+        res[name] = t
+        say(f"kernel={name}: matvec + precond {t:.3f} ms")
+    name = min(res, key=res.get)
+    settings = KERNELS[name](nrhs)
+    for k, v in settings.items():
+        ctx.tune(k, v)
+    best.update(settings)
+    timings["iteration_ms"] = res
     table = load_table(path)
-    table[_key(ctx, nrhs)] = {"params": best, "timings_ms": {k: {str(a): b for a, b in v.items()}
-                                                             for k, v in timings.items()}}
+    table[_key(ctx, nrhs)] = {"params": best, "kernel": name,
+                              "timings_ms": {k: {str(a): b for a, b in v.items()} for k, v in timings.items()}}
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as f:

@@ -140,6 +140,7 @@ void factor_leaves(hbf_ctx* c, hipStream_t s) {
   SuperleafOut so;
   const int64_t per = static_cast<int64_t>(n0) * n0 * (1 << P.sl) * ((1 << P.sl) + 1) / 2;
   so.per_superleaf = per;
+  so.slab = P.sl_slab;
   for (int set = 0; set < 4; ++set) so.base[set] = P.leaf_fac_begin + set * nsl * per;
   cd* dA = nullptr;
   cd* work = nullptr;
@@ -255,6 +256,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       a.src_cap = 0;
       a.ch = 0;
+      a.split = c->lane_split ? 1 : 0;
       hipError_t e;
       if (c->prog_pipe) {
         e = (c->dtype == HBF_C128) ? launch_prog_pipe_c128(a, c->d_steps, l.first, l.first + l.count, adjoint, s)
@@ -302,6 +304,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       a.src_cap = 0;
       a.ch = 0;
+      a.split = c->lane_split ? 1 : 0;
       hipError_t e;
       if (c->dtype == HBF_C128) e = launch_pipe_c128(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
       else if (vec_c128) e = launch_pipe_c64_hi(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
@@ -561,6 +564,16 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     // release the host copies of the factors
     fill_stats(P, &c->stats, c->elt);
     c->stats.bytes_index = static_cast<int64_t>(P.perm.size() + P.units.size() * sizeof(Unit));
+    {
+      const int64_t vec = 2 * N * static_cast<int64_t>(c->elt);
+      c->stats.apply_bytes_matvec = schedule_bytes(P, P.mv_fwd, nullptr, c->elt) + vec;
+      c->stats.launches_matvec = static_cast<int64_t>(P.mv_fwd.size());
+      c->stats.apply_bytes_precond =
+          c->prec == HBF_PREC_NONE
+              ? vec
+              : schedule_bytes(P, c->S.fwd, &c->S.steps, c->elt) + schedule_bytes(P, c->S.bwd, &c->S.steps, c->elt) +
+                    (c->prec == HBF_PREC_BLOCK_LU ? schedule_bytes(P, c->S.diag, nullptr, c->elt) : 0) + vec;
+    }
     std::vector<cplx>().swap(P.fac);
     hip_check(hipStreamSynchronize(s), "build sync");
     (void)hipStreamDestroy(s);
@@ -715,6 +728,7 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     return HBF_OK;
   }
   if (k == "wave_units") { c->wave_units = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "lane_split") { c->lane_split = value != 0; free_graphs(c); return HBF_OK; }
   if (k == "use_graphs") { c->use_graphs = value != 0; free_graphs(c); return HBF_OK; }
   if (k == "r1_max_blocks") {
     if (value < 1 || value > (1 << 20)) return fail(HBF_EINVAL, "hbf_tune: r1_max_blocks out of range");

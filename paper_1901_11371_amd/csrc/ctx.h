@@ -24,6 +24,7 @@ struct hbf_ctx {
   bool wave_units = true;      // one wave per group for one- or two-RHS launches
   bool r1_kernel = false;      // register-streaming kernel for one-RHS launches (LDS atomics)
   bool prog_pipe = true;       // pipelined wave teams in the sweep programs
+  bool lane_split = true;      // pipelined kernels: several lanes share one output of a small unit
   int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
   int r1_max_blocks = 2048;    // persistent grid size of that kernel
 

@@ -107,9 +107,12 @@ struct Plan {
   std::vector<int32_t> diag_unit;
   std::vector<int32_t> l0_lower_unit, l0_upper_unit;  // per pair of the last level
   // super-leaf solve units: super-leaf S of 2^sl leaves owns units
-  // [sl_*[S], sl_*[S] + 2^sl), one row block per leaf; matrices are filled by
-  // the leaf factorisation (on the device, or on the host for the checks)
+  // [sl_*[S], sl_*[S] + sl_units), one per slab of sl_slab rows of each leaf
+  // row block; matrices are filled by the leaf factorisation (on the device,
+  // or on the host for the checks)
   int sl = 2;
+  int sl_slab = 8;                // rows of a super-leaf unit (a slab of a leaf row block)
+  int sl_units = 0;               // units per super-leaf and set
   std::vector<int32_t> sl_fwd, sl_bwd, sl_adj_fwd, sl_adj_bwd;
   int64_t leaf_fac_begin = 0;     // first complex entry of the super-leaf region
   int64_t leaf_fac_len = 0;

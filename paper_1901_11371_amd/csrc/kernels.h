@@ -30,11 +30,12 @@ struct StageArgs {
   double alpha_re, alpha_im;
   int32_t ch;             // matrix chunk capacity (entries) in LDS
   int32_t src_cap;        // LDS source capacity (rows x rc entries)
+  int32_t split = 1;      // 1: up to 32 lanes may share one output of a small unit (pipelined kernels)
 };
 
 constexpr int kStageThreads = 256;
 constexpr int kOutPerThread = 4;
-constexpr int kProgWaves = 8;
+constexpr int kProgWaves = 16;
 constexpr int kProgThreads = 64 * kProgWaves;
 constexpr int kProgOutPerThread = 4;
 constexpr int kWaveOutPerThread = 4;
@@ -76,12 +77,14 @@ hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c1
 
 // Super-leaf factorisation in FP64 of super-leaves [S0, S0+nb): A holds their
 // exact diagonal blocks (row-major ns x ns each, batch-local); the inverses of
-// the lower and upper blocks of L~ / U~ are written as four row-block unit
-// sets at base[set] + S * per_superleaf (complex entries).  work holds
-// nb * 3 ns^2 complex doubles.
+// the lower and upper blocks of L~ / U~ are written as four unit sets at
+// base[set] + S * per_superleaf (complex entries): per leaf row block, slabs
+// of `slab` rows, each column-major slab x width.  work holds nb * 3 ns^2
+// complex doubles.
 struct SuperleafOut {
   int64_t base[4];
   int64_t per_superleaf;
+  int32_t slab;
 };
 hipError_t launch_superleaf_factor(const cd* A, int64_t S0, int64_t nb, int ns, int n0, int mode, double sre,
                                   double sim, void* fac, int fac_c128, SuperleafOut so, int* flag, cd* work,

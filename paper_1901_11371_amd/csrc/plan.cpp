@@ -690,15 +690,20 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
   // Super-leaf solve units.  The diagonal tree is cut at super-leaves of
   // 2^sl leaves; inside one, the block substitution of Algorithms 3 / 4 is
   // replaced by the inverse of that diagonal block of L~ (or U~), formed in
-  // FP64 from the exact entries and stored as one row block per leaf (a unit
-  // reading the super-leaf's input rows it depends on).  Four sets: forward
-  // (L inverse), backward (U inverse), and the conjugate transposes of the U
-  // and L inverses for the adjoint sweeps (those are applied in forward mode).
+  // FP64 from the exact entries.  Each leaf row block of the inverse is split
+  // into slabs of sl_slab rows, one unit each (reading the super-leaf's input
+  // rows the row block depends on), so that the solve of one super-leaf is
+  // spread over many independent units.  Four sets: forward (L inverse),
+  // backward (U inverse), and the conjugate transposes of the U and L
+  // inverses for the adjoint sweeps (those are applied in forward mode).
   // Matrices live in a region after the factors and are filled by the leaf
   // factorisation.
   const hbf_prec prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
   P.sl = std::min(2, P.V);
+  P.sl_slab = (leaf % 8 == 0) ? 8 : leaf;
   const int s_leaves = 1 << P.sl;
+  const int slabs = leaf / P.sl_slab;
+  P.sl_units = s_leaves * slabs;
   const int64_t ns = static_cast<int64_t>(leaf) << P.sl;
   const int64_t nsl = P.n / ns;
   for (auto* v : {&P.sl_fwd, &P.sl_bwd, &P.sl_adj_fwd, &P.sl_adj_bwd}) v->clear();
@@ -706,7 +711,6 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
   P.leaf_fac_len = 0;
   if (prec != HBF_PREC_NONE) {
     int64_t off = P.leaf_fac_begin;
-    const int64_t b2 = static_cast<int64_t>(leaf) * leaf;
     // set 0: lower-shaped forward, 1: upper-shaped backward, 2: lower-shaped
     // adjoint-forward, 3: upper-shaped adjoint-backward
     for (int set = 0; set < 4; ++set) {
@@ -715,20 +719,22 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
       for (int64_t S = 0; S < nsl; ++S) {
         dst.push_back(static_cast<int32_t>(P.units.size()));
         for (int i = 0; i < s_leaves; ++i) {
-          Unit u = blank_unit(UNIT_DENSE);
           const int c0 = lower_shape ? 0 : i;                 // first leaf column of the row block
           const int c1 = lower_shape ? i + 1 : s_leaves;      // end leaf column
-          u.in_buf = (set < 2) ? BUF_Y : BUF_X;
-          u.out_buf = (set < 2) ? BUF_X : BUF_Y;
-          u.in_off[0] = static_cast<int32_t>(S * ns + static_cast<int64_t>(c0) * leaf);
-          u.in_len[0] = static_cast<int16_t>((c1 - c0) * leaf);
-          u.out_off[0] = static_cast<int32_t>(S * ns + static_cast<int64_t>(i) * leaf);
-          u.out_len[0] = static_cast<int16_t>(leaf);
-          u.mat_len = static_cast<int32_t>(b2 * (c1 - c0));
-          u.mat = off;
-          off += u.mat_len;
-          u.perm = 0;
-          P.units.push_back(u);
+          for (int j = 0; j < slabs; ++j) {
+            Unit u = blank_unit(UNIT_DENSE);
+            u.in_buf = (set < 2) ? BUF_Y : BUF_X;
+            u.out_buf = (set < 2) ? BUF_X : BUF_Y;
+            u.in_off[0] = static_cast<int32_t>(S * ns + static_cast<int64_t>(c0) * leaf);
+            u.in_len[0] = static_cast<int16_t>((c1 - c0) * leaf);
+            u.out_off[0] = static_cast<int32_t>(S * ns + static_cast<int64_t>(i) * leaf + j * P.sl_slab);
+            u.out_len[0] = static_cast<int16_t>(P.sl_slab);
+            u.mat_len = static_cast<int32_t>(static_cast<int64_t>(P.sl_slab) * leaf * (c1 - c0));
+            u.mat = off;
+            off += u.mat_len;
+            u.perm = 0;
+            P.units.push_back(u);
+          }
         }
       }
     }

@@ -87,9 +87,9 @@ struct SweepGen {
       return;
     }
     if (dd == P.V - P.sl) {
-      // super-leaf solve: one row-block unit per leaf, all independent; the
+      // super-leaf solve: one unit per row slab, all independent; the
       // adjoint sweeps use the stored conjugate-transposed sets in forward mode
-      emit(leaf_units[idx], leaf_units[idx] + (1 << P.sl), 0, 1, prog, adjoint ? 1 : 0);
+      emit(leaf_units[idx], leaf_units[idx] + P.sl_units, 0, 1, prog, adjoint ? 1 : 0);
       return;
     }
     const int64_t first = lower_dir ? 2 * idx : 2 * idx + 1;
@@ -254,6 +254,29 @@ void unit_eval(const Plan& P, const Unit& u, bool adj, const std::vector<cplx>& 
 
 }  // namespace
 
+int64_t schedule_bytes(const Plan& P, const std::vector<Launch>& launches, const std::vector<int32_t>* steps,
+                       int elt) {
+  int64_t total = 0;
+  auto add = [&](int32_t uid) {
+    const Unit& u = P.units[uid];
+    total += static_cast<int64_t>(u.mat_len) * elt + static_cast<int64_t>(sizeof(Unit));
+    if (u.type == UNIT_GATHER) total += 2 * (u.in_len[0] + u.in_len[1]);
+    if (u.type == UNIT_SCATTER) total += 2 * (u.out_len[0] + u.out_len[1]);
+  };
+  for (const Launch& L : launches) {
+    if (L.prog) {
+      for (int st = L.first; st < L.first + L.count; ++st)
+        for (int32_t q = (*steps)[3 * st]; q < (*steps)[3 * st + 1]; ++q) add(q);
+    } else if (L.direct) {
+      for (int32_t q = L.first; q < L.first + L.count; ++q) add(q);
+    } else {
+      for (int g = L.first; g < L.first + L.count; ++g)
+        for (int32_t q = P.group_off[g]; q < P.group_off[g + 1]; ++q) add(P.group_units[q]);
+    }
+  }
+  return total;
+}
+
 void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
                cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps) {
   auto bufp = [&](uint8_t id) -> cplx* { return id == BUF_X ? X : id == BUF_Y ? Y : arena; };
@@ -360,24 +383,24 @@ static void invert_dense(std::vector<cplx>& A, int n) {
 // Fill the four super-leaf sets from the inverses Linv (of the lower block)
 // and Uinv (of the upper block) of super-leaf S (both row-major ns x ns).
 void store_superleaf(Plan& P, int64_t S, const std::vector<cplx>& Linv, const std::vector<cplx>& Uinv) {
-  const int n0 = P.n0;
-  const int s_leaves = 1 << P.sl;
-  const int64_t ns = static_cast<int64_t>(n0) << P.sl;
+  const int64_t ns = static_cast<int64_t>(P.n0) << P.sl;
   for (int set = 0; set < 4; ++set) {
     const std::vector<int32_t>& first = set == 0 ? P.sl_fwd : set == 1 ? P.sl_bwd : set == 2 ? P.sl_adj_fwd : P.sl_adj_bwd;
-    for (int i = 0; i < s_leaves; ++i) {
-      const Unit& u = P.units[first[S] + i];
-      const int c0 = (u.in_off[0] - static_cast<int32_t>(S * ns));
+    for (int q = 0; q < P.sl_units; ++q) {
+      const Unit& u = P.units[first[S] + q];
+      const int r0 = u.out_off[0] - static_cast<int32_t>(S * ns);
+      const int rows = u.out_len[0];
+      const int c0 = u.in_off[0] - static_cast<int32_t>(S * ns);
       const int w = u.in_len[0];
       for (int c = 0; c < w; ++c)
-        for (int r = 0; r < n0; ++r) {
-          const int64_t gr = static_cast<int64_t>(i) * n0 + r, gc = c0 + c;
+        for (int r = 0; r < rows; ++r) {
+          const int64_t gr = r0 + r, gc = c0 + c;
           cplx v;
           if (set == 0) v = Linv[gr * ns + gc];
           else if (set == 1) v = Uinv[gr * ns + gc];
           else if (set == 2) v = std::conj(Uinv[gc * ns + gr]);
           else v = std::conj(Linv[gc * ns + gr]);
-          P.fac[u.mat + static_cast<int64_t>(c) * n0 + r] = v;
+          P.fac[u.mat + static_cast<int64_t>(c) * rows + r] = v;
         }
     }
   }

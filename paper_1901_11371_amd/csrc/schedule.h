@@ -25,6 +25,10 @@ void build_sweeps(const Plan& P, Sweeps& S, int prog_levels = 6);
 void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
                cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps = nullptr);
 
+// Bytes a schedule streams once per application: matrices (elt bytes per
+// entry), permutations and descriptors of every unit it runs.
+int64_t schedule_bytes(const Plan& P, const std::vector<Launch>& launches, const std::vector<int32_t>* steps, int elt);
+
 void host_leaf_factor(Plan& P, hbf_prec prec);
 void superleaf_blocks(const Plan& P, const std::vector<cplx>& A, hbf_prec prec, std::vector<cplx>& Lm,
                       std::vector<cplx>& Um);

@@ -483,7 +483,7 @@ __device__ void gauss_jordan_inplace(cd* W, int n, bool pivot, int* flag) {
 // the exact entries of the super-leaf's diagonal block (row-major ns x ns).
 // The lower and upper blocks of L~ / U~ are inverted by Gauss-Jordan (with
 // partial pivoting in the block reading, where they have full n0 x n0
-// diagonal blocks) and written as the four row-block unit sets.
+// diagonal blocks) and written as the four unit sets (row slabs).
 template <class F>
 __global__ void __launch_bounds__(256) k_superleaf_factor(const cd* A, int64_t S0, int ns, int n0, int mode,
                                                           double sre, double sim, cx<F>* fac, SuperleafOut so,
@@ -534,9 +534,11 @@ __global__ void __launch_bounds__(256) k_superleaf_factor(const cd* A, int64_t S
     for (int i = 0; i < sl; ++i) {
       const int c0 = lower_shape ? 0 : i * n0;
       const int wid = lower_shape ? (i + 1) * n0 : (sl - i) * n0;
+      const int sw = so.slab * wid;  // entries of one slab (column-major slab x wid)
       for (int e = tid; e < n0 * wid; e += blockDim.x) {
-        const int c = e / n0, r = e - c * n0;
-        const int gr = i * n0 + r, gc = c0 + c;
+        const int j = e / sw, rem = e - j * sw;
+        const int c = rem / so.slab, r = rem - c * so.slab;
+        const int gr = i * n0 + j * so.slab + r, gc = c0 + c;
         cd v;
         if (set == 0) v = Linv[static_cast<int64_t>(gr) * ns + gc];
         else if (set == 1) v = W[static_cast<int64_t>(gr) * w + ns + gc];

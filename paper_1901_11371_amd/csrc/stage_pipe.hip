@@ -20,6 +20,8 @@ constexpr int kChunkW = 64 * kPW;       // words per chunk (4 KB)
 constexpr int kSrcPL = 4;               // source entries per lane (256 max)
 constexpr int kPermPL = 8;              // permutation bytes per lane (512 max)
 constexpr int kOpt = 4;                 // outputs per lane (256 max)
+constexpr int kStepWin = 256;           // program steps staged in LDS at a time
+constexpr int kDescMax = 64;            // unit descriptors per program step staged in LDS
 
 template <class T>
 __device__ __forceinline__ void cmac(cx<T>& acc, cx<T> a, cx<T> b) {
@@ -88,6 +90,17 @@ __device__ __forceinline__ UDesc read_desc(const Unit* U) {
   return d;
 }
 
+// A unit descriptor staged in LDS, moved to scalar registers.
+__device__ __forceinline__ Unit unit_from_lds(const Unit* p) {
+  const int* w = reinterpret_cast<const int*>(p);
+  int v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = uni(w[i]);
+  Unit u;
+  __builtin_memcpy(&u, v, sizeof(Unit));
+  return u;
+}
+
 // The register slot of one prefetched work item.
 template <class V>
 struct Slot {
@@ -104,8 +117,7 @@ struct Cursor {
 };
 
 template <class F, class V, class A, bool ADJ>
-__device__ __forceinline__ void issue(const StageArgs& a, const UDesc& d, int c, int lane, int R, int r0, int nr,
-                                      Slot<V>& s) {
+__device__ __forceinline__ void issue_static(const StageArgs& a, const UDesc& d, int c, int lane, Slot<V>& s) {
   const u32x4* gm = reinterpret_cast<const u32x4*>(reinterpret_cast<const cx<F>*>(a.fac) + d.mat);
 #pragma unroll
   for (int j = 0; j < kPW; ++j) {
@@ -113,21 +125,221 @@ __device__ __forceinline__ void issue(const StageArgs& a, const UDesc& d, int c,
     if (w < d.nwords) s.mw[j] = __builtin_nontemporal_load(&gm[w]);
   }
   if (c == 0) {
-    const V* sb = reinterpret_cast<const V*>(a.buf[d.s_buf]);
-#pragma unroll
-    for (int j = 0; j < kSrcPL; ++j) {
-      const int e = lane + 64 * j;
-      if (e < d.n_src * nr) {
-        const int t = e / nr, rr = e - t * nr;
-        const int row = (t < d.s_len0) ? d.s_off0 + t : d.s_off1 + (t - d.s_len0);
-        s.sv[j] = sb[static_cast<int64_t>(row) * R + r0 + rr];
-      }
-    }
 #pragma unroll
     for (int j = 0; j < kPermPL; ++j) {
       const int e = lane + 64 * j;
       if (e < 2 * d.plen) s.pv[j] = a.perm[d.perm + e];
     }
+  }
+}
+
+template <class F, class V, class A, bool ADJ>
+__device__ __forceinline__ void issue_src(const StageArgs& a, const UDesc& d, int lane, int R, int r0, int nr,
+                                          Slot<V>& s) {
+  const V* sb = reinterpret_cast<const V*>(a.buf[d.s_buf]);
+#pragma unroll
+  for (int j = 0; j < kSrcPL; ++j) {
+    const int e = lane + 64 * j;
+    if (e < d.n_src * nr) {
+      const int t = e / nr, rr = e - t * nr;
+      const int row = (t < d.s_len0) ? d.s_off0 + t : d.s_off1 + (t - d.s_len0);
+      s.sv[j] = sb[static_cast<int64_t>(row) * R + r0 + rr];
+    }
+  }
+}
+
+template <class F, class V, class A, bool ADJ>
+__device__ __forceinline__ void issue(const StageArgs& a, const UDesc& d, int c, int lane, int R, int r0, int nr,
+                                      Slot<V>& s) {
+  issue_static<F, V, A, ADJ>(a, d, c, lane, s);
+  if (c == 0) issue_src<F, V, A, ADJ>(a, d, lane, R, r0, nr, s);
+}
+
+// Stage the slot's item in LDS (sources and permutations for a unit's first chunk).
+template <class F, class V, class A>
+__device__ __forceinline__ void commit(const UDesc& d, int c, int lane, int nr, const Slot<V>& slot, cx<A>* s_src,
+                                       uint8_t* s_p, uint8_t* s_q, u32x4* s_m4) {
+  if (c == 0) {
+#pragma unroll
+    for (int j = 0; j < kSrcPL; ++j) {
+      const int e = lane + 64 * j;
+      if (e < d.n_src * nr) s_src[e] = up<A>(slot.sv[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kPermPL; ++j) {
+      const int e = lane + 64 * j;
+      if (e < 2 * d.plen) {
+        const int o = e / d.plen, p = e - o * d.plen;
+        s_p[o * 256 + p] = slot.pv[j];
+        s_q[o * 256 + slot.pv[j]] = static_cast<uint8_t>(p);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kPW; ++j) {
+    const int w = c * kChunkW + lane + 64 * j;
+    if (w < d.nwords) s_m4[lane + 64 * j] = slot.mw[j];
+  }
+}
+
+// Accumulate one item (a matrix chunk of one unit) into the lane's outputs.
+// Lanes per output: with fewer than 64 outputs, P = 2^i lanes share one
+// output's dot product (each takes every P-th term); write_dst reduces them.
+// Only for items that are written on their own (`split`): the units of a
+// group accumulate into the same registers and must agree on the mapping.
+__device__ __forceinline__ int lanes_per_output(int nout, bool split) {
+  int P = 1;
+  if (split)
+    while (P < 32 && nout * P * 2 <= 64) P *= 2;
+  return P;
+}
+
+template <class F, class A, bool ADJ>
+__device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, int nr, const cx<A>* s_src,
+                                             const uint8_t* s_p, const uint8_t* s_q, const cx<F>* s_mat,
+                                             cx<A>* acc, bool split) {
+  constexpr int kChunkE = kChunkW * 16 / static_cast<int>(sizeof(cx<F>));
+  const int e0 = c * kChunkE;
+  const int e1 = min(d.mat_len, e0 + kChunkE);
+  const int type = d.type;
+  const int k0 = d.k0, k1 = d.k1, f_in = d.f_in, f_out = d.f_out;
+  const int P = lanes_per_output(d.n_dst * nr, split);
+  const int part = lane & (P - 1);
+  const bool first_chunk = (c == 0) && part == 0;
+#pragma unroll
+  for (int j = 0; j < kOpt; ++j) {
+    const int p = (P > 1) ? (lane / P) : lane + 64 * j;
+    if (P > 1 && j > 0) break;
+    if (p >= d.n_dst * nr) break;
+    const int o = p / nr;
+    const int rr = p - o * nr;
+    cx<A> s = acc[j];
+    auto S = [&](int t) { return s_src[t * nr + rr]; };
+    auto MAC = [&](int e, int t) {
+      const cx<A> m = up<A>(s_mat[e - e0]);
+      if (ADJ) cmac_conj(s, m, S(t));
+      else cmac(s, m, S(t));
+    };
+    if (type == UNIT_DENSE) {
+      if (!ADJ) {
+        const int tlo = cdiv_pos(e0 - o, f_out), thi = min(f_in, cdiv_pos(e1 - o, f_out));
+        for (int t = tlo + part; t < thi; t += P) MAC(t * f_out + o, t);
+      } else {
+        const int base = o * f_out;
+        const int ilo = max(0, e0 - base), ihi = min(f_out, e1 - base);
+        for (int i = ilo + part; i < ihi; i += P) MAC(base + i, i);
+      }
+    } else if (type == UNIT_GATHER) {
+      if (!ADJ) {
+        const int id = (o < k0) ? 0 : 1;
+        const int i = id ? o - k0 : o;
+        const int k = id ? k1 : k0;
+        const int r = f_in - k;
+        const int base = id ? k0 * (f_in - k0) : 0;
+        const uint8_t* pm = s_p + id * 256;
+        if (first_chunk) {
+          const cx<A> v = S(pm[i]);
+          s.x += v.x;
+          s.y += v.y;
+        }
+        const int tlo = cdiv_pos(e0 - base - i, k), thi = min(r, cdiv_pos(e1 - base - i, k));
+        for (int t = tlo + part; t < thi; t += P) MAC(base + t * k + i, pm[k + t]);
+      } else {
+#pragma unroll
+        for (int id = 0; id < 2; ++id) {
+          const int k = id ? k1 : k0;
+          const int base = id ? k0 * (f_in - k0) : 0;
+          const int sbase = id ? k0 : 0;
+          const int qq = s_q[id * 256 + o];
+          if (qq < k) {
+            if (first_chunk) {
+              const cx<A> v = S(sbase + qq);
+              s.x += v.x;
+              s.y += v.y;
+            }
+          } else {
+            const int cb = base + (qq - k) * k;
+            const int ilo = max(0, e0 - cb), ihi = min(k, e1 - cb);
+            for (int i = ilo + part; i < ihi; i += P) MAC(cb + i, sbase + i);
+          }
+        }
+      }
+    } else {  // UNIT_SCATTER
+      if (!ADJ) {
+#pragma unroll
+        for (int id = 0; id < 2; ++id) {
+          const int k = id ? k1 : k0;
+          const int r = f_out - k;
+          const int base = id ? k0 * (f_out - k0) : 0;
+          const int sbase = id ? k0 : 0;
+          const int qq = s_p[id * 256 + o];
+          if (qq < k) {
+            if (first_chunk) {
+              const cx<A> v = S(sbase + qq);
+              s.x += v.x;
+              s.y += v.y;
+            }
+          } else {
+            const int t = qq - k;
+            const int jlo = cdiv_pos(e0 - base - t, r), jhi = min(k, cdiv_pos(e1 - base - t, r));
+            for (int jj = jlo + part; jj < jhi; jj += P) MAC(base + jj * r + t, sbase + jj);
+          }
+        }
+      } else {
+        const int id = (o < k0) ? 0 : 1;
+        const int jj = id ? o - k0 : o;
+        const int k = id ? k1 : k0;
+        const int r = f_out - k;
+        const int base = id ? k0 * (f_out - k0) : 0;
+        const uint8_t* pm = s_q + id * 256;
+        if (first_chunk) {
+          const cx<A> v = S(pm[jj]);
+          s.x += v.x;
+          s.y += v.y;
+        }
+        const int rb = base + jj * r;
+        const int tlo = max(0, e0 - rb), thi = min(r, e1 - rb);
+        for (int t = tlo + part; t < thi; t += P) MAC(rb + t, pm[k + t]);
+      }
+    }
+    acc[j] = s;
+  }
+}
+
+// Write a finished unit's (or group's) destination and clear the accumulators.
+template <class V, class A>
+__device__ __forceinline__ void write_dst(const StageArgs& a, const UDesc& d, int acc_mode, double alpha_re,
+                                          double alpha_im, int lane, int R, int r0, int nr, cx<A>* acc,
+                                          bool split) {
+  V* db = reinterpret_cast<V*>(a.buf[d.d_buf]);
+  const A are = static_cast<A>(alpha_re), aim = static_cast<A>(alpha_im);
+  const int P = lanes_per_output(d.n_dst * nr, split);
+  if (P > 1) {
+    for (int off = P / 2; off >= 1; off /= 2) {
+      acc[0].x += __shfl_xor(acc[0].x, off);
+      acc[0].y += __shfl_xor(acc[0].y, off);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kOpt; ++j) {
+    const int p = (P > 1) ? (lane / P) : lane + 64 * j;
+    if (P > 1 && (j > 0 || (lane & (P - 1)) != 0)) {
+      acc[j] = cx<A>{0, 0};
+      continue;
+    }
+    if (p >= d.n_dst * nr) break;
+    const int o = p / nr;
+    const int rr = p - o * nr;
+    const int row = (o < d.d_len0) ? d.d_off0 + o : d.d_off1 + (o - d.d_len0);
+    V* dp = &db[static_cast<int64_t>(row) * R + r0 + rr];
+    cx<A> v = acc[j];
+    if (acc_mode) {
+      const cx<A> cu = up<A>(*dp);
+      v = cx<A>{cu.x + are * v.x - aim * v.y, cu.y + are * v.y + aim * v.x};
+    }
+    using VT = decltype(dp->x);
+    *dp = V{static_cast<VT>(v.x), static_cast<VT>(v.y)};
+    acc[j] = cx<A>{0, 0};
   }
 }
 
@@ -169,29 +381,8 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
   for (int j = 0; j < kOpt; ++j) acc[j] = cx<A>{0, 0};
 
   for (;;) {
-    // ---- commit the current item to LDS ----
     const int nch = d.nwords > 0 ? (d.nwords + kChunkW - 1) / kChunkW : 1;
-    if (cur.c == 0) {
-#pragma unroll
-      for (int j = 0; j < kSrcPL; ++j) {
-        const int e = lane + 64 * j;
-        if (e < d.n_src * nr) s_src[e] = up<A>(slot.sv[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < kPermPL; ++j) {
-        const int e = lane + 64 * j;
-        if (e < 2 * d.plen) {
-          const int o = e / d.plen, p = e - o * d.plen;
-          s_p[o * 256 + p] = slot.pv[j];
-          s_q[o * 256 + slot.pv[j]] = static_cast<uint8_t>(p);
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kPW; ++j) {
-      const int w = cur.c * kChunkW + lane + 64 * j;
-      if (w < d.nwords) s_m4[lane + 64 * j] = slot.mw[j];
-    }
+    commit<F, V, A>(d, cur.c, lane, nr, slot, s_src, s_p, s_q, s_m4);
     wsync();
     // ---- advance the cursor and prefetch the next item ----
     Cursor nxt = cur;
@@ -216,137 +407,152 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
       if (nxt.c == 0) dn = read_desc<ADJ, F>(unit_of(nxt.q));
       issue<F, V, A, ADJ>(a, dn, nxt.c, lane, R, r0, nr, slot);
     }
-    // ---- compute the current item ----
-    {
-      const int e0 = cur.c * kChunkE;
-      const int e1 = min(d.mat_len, e0 + kChunkE);
-      const bool first_chunk = cur.c == 0;
-      const int type = d.type;
-      const int k0 = d.k0, k1 = d.k1, f_in = d.f_in, f_out = d.f_out;
-#pragma unroll
-      for (int j = 0; j < kOpt; ++j) {
-        const int p = lane + 64 * j;
-        if (p >= d.n_dst * nr) break;
-        const int o = p / nr;
-        const int rr = p - o * nr;
-        cx<A> s = acc[j];
-        auto S = [&](int t) { return s_src[t * nr + rr]; };
-        auto MAC = [&](int e, int t) {
-          const cx<A> m = up<A>(s_mat[e - e0]);
-          if (ADJ) cmac_conj(s, m, S(t));
-          else cmac(s, m, S(t));
-        };
-        if (type == UNIT_DENSE) {
-          if (!ADJ) {
-            const int tlo = cdiv_pos(e0 - o, f_out), thi = min(f_in, cdiv_pos(e1 - o, f_out));
-            for (int t = tlo; t < thi; ++t) MAC(t * f_out + o, t);
-          } else {
-            const int base = o * f_out;
-            const int ilo = max(0, e0 - base), ihi = min(f_out, e1 - base);
-            for (int i = ilo; i < ihi; ++i) MAC(base + i, i);
-          }
-        } else if (type == UNIT_GATHER) {
-          if (!ADJ) {
-            const int id = (o < k0) ? 0 : 1;
-            const int i = id ? o - k0 : o;
-            const int k = id ? k1 : k0;
-            const int r = f_in - k;
-            const int base = id ? k0 * (f_in - k0) : 0;
-            const uint8_t* pm = s_p + id * 256;
-            if (first_chunk) {
-              const cx<A> v = S(pm[i]);
-              s.x += v.x;
-              s.y += v.y;
-            }
-            const int tlo = cdiv_pos(e0 - base - i, k), thi = min(r, cdiv_pos(e1 - base - i, k));
-            for (int t = tlo; t < thi; ++t) MAC(base + t * k + i, pm[k + t]);
-          } else {
-#pragma unroll
-            for (int id = 0; id < 2; ++id) {
-              const int k = id ? k1 : k0;
-              const int base = id ? k0 * (f_in - k0) : 0;
-              const int sbase = id ? k0 : 0;
-              const int qq = s_q[id * 256 + o];
-              if (qq < k) {
-                if (first_chunk) {
-                  const cx<A> v = S(sbase + qq);
-                  s.x += v.x;
-                  s.y += v.y;
-                }
-              } else {
-                const int cb = base + (qq - k) * k;
-                const int ilo = max(0, e0 - cb), ihi = min(k, e1 - cb);
-                for (int i = ilo; i < ihi; ++i) MAC(cb + i, sbase + i);
-              }
-            }
-          }
-        } else {  // UNIT_SCATTER
-          if (!ADJ) {
-#pragma unroll
-            for (int id = 0; id < 2; ++id) {
-              const int k = id ? k1 : k0;
-              const int r = f_out - k;
-              const int base = id ? k0 * (f_out - k0) : 0;
-              const int sbase = id ? k0 : 0;
-              const int qq = s_p[id * 256 + o];
-              if (qq < k) {
-                if (first_chunk) {
-                  const cx<A> v = S(sbase + qq);
-                  s.x += v.x;
-                  s.y += v.y;
-                }
-              } else {
-                const int t = qq - k;
-                const int jlo = cdiv_pos(e0 - base - t, r), jhi = min(k, cdiv_pos(e1 - base - t, r));
-                for (int jj = jlo; jj < jhi; ++jj) MAC(base + jj * r + t, sbase + jj);
-              }
-            }
-          } else {
-            const int id = (o < k0) ? 0 : 1;
-            const int jj = id ? o - k0 : o;
-            const int k = id ? k1 : k0;
-            const int r = f_out - k;
-            const int base = id ? k0 * (f_out - k0) : 0;
-            const uint8_t* pm = s_q + id * 256;
-            if (first_chunk) {
-              const cx<A> v = S(pm[jj]);
-              s.x += v.x;
-              s.y += v.y;
-            }
-            const int rb = base + jj * r;
-            const int tlo = max(0, e0 - rb), thi = min(r, e1 - rb);
-            for (int t = tlo; t < thi; ++t) MAC(rb + t, pm[k + t]);
-          }
-        }
-        acc[j] = s;
-      }
-    }
-    // ---- end of a group: write its destination ----
-    if (group_end) {
-      V* db = reinterpret_cast<V*>(a.buf[d.d_buf]);
-      const A are = static_cast<A>(a.alpha_re), aim = static_cast<A>(a.alpha_im);
-#pragma unroll
-      for (int j = 0; j < kOpt; ++j) {
-        const int p = lane + 64 * j;
-        if (p >= d.n_dst * nr) break;
-        const int o = p / nr;
-        const int rr = p - o * nr;
-        const int row = (o < d.d_len0) ? d.d_off0 + o : d.d_off1 + (o - d.d_len0);
-        V* dp = &db[static_cast<int64_t>(row) * R + r0 + rr];
-        cx<A> v = acc[j];
-        if (a.acc) {
-          const cx<A> cu = up<A>(*dp);
-          v = cx<A>{cu.x + are * v.x - aim * v.y, cu.y + are * v.y + aim * v.x};
-        }
-        using VT = decltype(dp->x);
-        *dp = V{static_cast<VT>(v.x), static_cast<VT>(v.y)};
-        acc[j] = cx<A>{0, 0};
-      }
-    }
+    compute_item<F, A, ADJ>(d, cur.c, lane, nr, s_src, s_p, s_q, s_mat, acc, a.direct && a.split);
+    if (group_end) write_dst<V, A>(a, d, a.acc, a.alpha_re, a.alpha_im, lane, R, r0, nr, acc, a.direct && a.split);
     wsync();
     if (nxt.q < 0) break;
     cur = nxt;
     d = dn;
+  }
+}
+
+// A sweep program run by one workgroup per RHS chunk: steps in order, each a
+// range of independent units shared by the waves (unit u0 + wave + kProgWaves i).
+// The step table is staged in LDS in windows of kStepWin steps, and the
+// descriptors of the first kDescMax units of each step in a ring of three
+// step buffers, loaded two steps ahead.  A wave prefetches one item ahead:
+// the next chunk, its next unit of the same step, or its first unit of the
+// next step (also when it has nothing to do in the current one); the
+// permutations and matrix chunk of that item are requested before the step
+// barrier (they do not depend on the sweep), its sources only after.
+template <class F, class V, class A, bool ADJ>
+__device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave, int lane,
+                         unsigned char* lds, int32_t* s_steps, Unit* ring, int R, int r0, int nr) {
+  cx<A>* s_src = reinterpret_cast<cx<A>*>(lds);
+  uint8_t* s_p = reinterpret_cast<uint8_t*>(s_src + 256);
+  uint8_t* s_q = s_p + 512;
+  u32x4* s_m4 = reinterpret_cast<u32x4*>(s_q + 512);
+  const cx<F>* s_mat = reinterpret_cast<const cx<F>*>(s_m4);
+  const int tid = threadIdx.x;
+  int w0 = s0;  // first step of the staged window
+  auto load_window = [&](int from) {
+    const int cnt = 3 * min(kStepWin, s1 - from);
+    for (int e = tid; e < cnt; e += blockDim.x) s_steps[e] = steps[3 * from + e];
+  };
+  auto st_u0 = [&](int st) { return uni(s_steps[3 * (st - w0)]); };
+  auto st_u1 = [&](int st) { return uni(s_steps[3 * (st - w0) + 1]); };
+  auto st_fl = [&](int st) { return uni(s_steps[3 * (st - w0) + 2]); };
+  // descriptor of unit q of step st, in the orientation the step applies it in
+  auto desc_at = [&](int q, int st) -> UDesc {
+    const int i = q - st_u0(st);
+    const int fl = st_fl(st);
+    Unit u;
+    if (i < kDescMax) u = unit_from_lds(&ring[(st % 3) * kDescMax + i]);
+    else u = a.units[q];
+    if (ADJ && ((fl >> 1) & 1)) return read_desc<false, F>(&u);
+    return read_desc<ADJ, F>(&u);
+  };
+  // ring slot of step st <- descriptors of its first kDescMax units (16 bytes per thread)
+  auto ring_src = [&](int st, u32x4& v) -> bool {
+    const int b0 = st_u0(st), nu = min(kDescMax, st_u1(st) - b0);
+    if (tid >= 4 * nu) return false;
+    v = reinterpret_cast<const u32x4*>(a.units + b0 + (tid >> 2))[tid & 3];
+    return true;
+  };
+  auto ring_put = [&](int st, const u32x4& v) {
+    reinterpret_cast<u32x4*>(ring + (st % 3) * kDescMax + (tid >> 2))[tid & 3] = v;
+  };
+  load_window(s0);
+  __syncthreads();
+  for (int st = s0; st < min(s1, s0 + 2); ++st) {
+    u32x4 v;
+    if (ring_src(st, v)) ring_put(st, v);
+  }
+  __syncthreads();
+  bool have = false;       // the item (cq, cc) of step cst has been requested
+  bool src_ready = false;  // ... including its sources
+  int cq = 0, cc = 0, cst = s0;
+  UDesc d{};
+  Slot<V> slot;
+  cx<A> acc[kOpt];
+#pragma unroll
+  for (int j = 0; j < kOpt; ++j) acc[j] = cx<A>{0, 0};
+  for (int st = s0; st < s1; ++st) {
+    if (st + 2 >= w0 + kStepWin && st + 2 < s1) {
+      // every wave has passed the previous step's barrier: no reads of the old window remain
+      w0 = st;
+      load_window(st);
+      __syncthreads();
+    }
+    u32x4 rv;
+    const bool rload = (st + 2 < s1) && ring_src(st + 2, rv);
+    const int u0 = st_u0(st), u1 = st_u1(st), flags = st_fl(st);
+    if (!have && u0 + wave < u1) {
+      cq = u0 + wave;
+      cc = 0;
+      cst = st;
+      d = desc_at(cq, st);
+      issue_static<F, V, A, ADJ>(a, d, 0, lane, slot);
+      have = true;
+      src_ready = false;
+    }
+    while (have && cst == st) {
+      if (cc == 0 && !src_ready) issue_src<F, V, A, ADJ>(a, d, lane, R, r0, nr, slot);
+      const int nch = d.nwords > 0 ? (d.nwords + kChunkW - 1) / kChunkW : 1;
+      commit<F, V, A>(d, cc, lane, nr, slot, s_src, s_p, s_q, s_m4);
+      wsync();
+      // next item
+      int nq = cq, nc = cc + 1, nst = st;
+      bool nhave = true;
+      bool unit_end = false;
+      if (nc >= nch) {
+        unit_end = true;
+        nc = 0;
+        if (cq + kProgWaves < u1) {
+          nq = cq + kProgWaves;
+        } else if (st + 1 < s1 && st_u0(st + 1) + wave < st_u1(st + 1)) {
+          nq = st_u0(st + 1) + wave;
+          nst = st + 1;
+        } else {
+          nhave = false;
+        }
+      }
+      UDesc dn = d;
+      src_ready = false;
+      if (nhave) {
+        if (nc == 0) dn = desc_at(nq, nst);
+        issue_static<F, V, A, ADJ>(a, dn, nc, lane, slot);
+        if (nc == 0 && nst == st) {  // same step: its sources are final already
+          issue_src<F, V, A, ADJ>(a, dn, lane, R, r0, nr, slot);
+          src_ready = true;
+        }
+      }
+      const bool fwd = ADJ && ((flags >> 1) & 1);
+      if (fwd) compute_item<F, A, false>(d, cc, lane, nr, s_src, s_p, s_q, s_mat, acc, a.split);
+      else compute_item<F, A, ADJ>(d, cc, lane, nr, s_src, s_p, s_q, s_mat, acc, a.split);
+      if (unit_end) {
+        const double are = (flags & 1) ? a.alpha_re : 0.0, aim = (flags & 1) ? a.alpha_im : 0.0;
+        write_dst<V, A>(a, d, flags & 1, are, aim, lane, R, r0, nr, acc, a.split);
+      }
+      wsync();
+      have = nhave;
+      cq = nq;
+      cc = nc;
+      cst = nst;
+      d = dn;
+    }
+    // a wave without work in this step requests its first item of the next one
+    if (!have && st + 1 < s1 && st_u0(st + 1) + wave < st_u1(st + 1)) {
+      cq = st_u0(st + 1) + wave;
+      cc = 0;
+      cst = st + 1;
+      d = desc_at(cq, st + 1);
+      issue_static<F, V, A, ADJ>(a, d, 0, lane, slot);
+      have = true;
+      src_ready = false;
+    }
+    if (rload) ring_put(st + 2, rv);
+    __syncthreads();
   }
 }
 
@@ -365,8 +571,7 @@ __global__ void __launch_bounds__(256) k_stage_pipe(StageArgs a, int ngroups, in
                          r0, nr);
 }
 
-// Sweep program: one workgroup per RHS chunk runs the steps in order; the
-// waves share each step's units (one unit per team).
+// Sweep program kernel: one workgroup per RHS chunk.
 template <class F, class V, class A, bool ADJ>
 __global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, const int32_t* steps, int s0, int s1,
                                                                   int team_lds) {
@@ -376,21 +581,10 @@ __global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, c
   const int chunk = blockIdx.x;
   const int r0 = chunk * a.rc;
   const int nr = min(a.rc, a.R - r0);
-  unsigned char* my = smem + static_cast<size_t>(wave) * team_lds;
-  const double are = a.alpha_re, aim = a.alpha_im;
-  for (int st = s0; st < s1; ++st) {
-    const int u0 = uni(steps[3 * st]), u1 = uni(steps[3 * st + 1]), flags = uni(steps[3 * st + 2]);
-    StageArgs b = a;
-    b.acc = flags & 1;
-    b.alpha_re = (flags & 1) ? are : 0.0;
-    b.alpha_im = (flags & 1) ? aim : 0.0;
-    b.direct = 1;
-    if (ADJ && ((flags >> 1) & 1))
-      team_run<F, V, A, false>(b, u0, u1 - u0, wave, kProgWaves, lane, my, a.R, r0, nr);
-    else
-      team_run<F, V, A, ADJ>(b, u0, u1 - u0, wave, kProgWaves, lane, my, a.R, r0, nr);
-    __syncthreads();
-  }
+  Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(kProgWaves) * team_lds);
+  int32_t* s_steps = reinterpret_cast<int32_t*>(ring + 3 * kDescMax);
+  prog_run<F, V, A, ADJ>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps, ring,
+                         a.R, r0, nr);
 }
 
 }  // namespace
@@ -418,12 +612,12 @@ static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int
                                    hipStream_t s) {
   const int lds1 = pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
   const dim3 grid(static_cast<unsigned>(a.nchunks));
+  const size_t lds =
+      static_cast<size_t>(lds1) * kProgWaves + 3 * kDescMax * sizeof(Unit) + 3 * sizeof(int32_t) * kStepWin;
   if (adjoint)
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, true>), grid, dim3(64 * kProgWaves), lds1 * kProgWaves, s, a, steps,
-                       s0, s1, lds1);
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, true>), grid, dim3(64 * kProgWaves), lds, s, a, steps, s0, s1, lds1);
   else
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, false>), grid, dim3(64 * kProgWaves), lds1 * kProgWaves, s, a, steps,
-                       s0, s1, lds1);
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, false>), grid, dim3(64 * kProgWaves), lds, s, a, steps, s0, s1, lds1);
   return hipGetLastError();
 }
 

@@ -115,6 +115,45 @@ def test_precond_matches_oracle(torch, spiral, prec, dtype):
     ctx.close()
 
 
+TUNINGS = [
+    {"prog_levels": 0},
+    {"prog_levels": 2},
+    {"prog_levels": 3, "lane_split": 0},
+    {"prog_levels": 12},
+    {"prog_pipe": 0},
+    {"pipe_max_r": 0, "wave_units": 1},
+    {"pipe_max_r": 0, "wave_units": 0},
+    {"use_graphs": 0, "prog_levels": 4},
+]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: ",".join(f"{k}={v}" for k, v in t.items()))
+def test_execution_parameters_keep_results(torch, spiral, tuning):
+    """Every execution parameter the autotuner may pick gives the oracle's
+    matvec and preconditioner (forward and adjoint, 1 and 5 RHS)."""
+    c, A = spiral
+    _say(f"[tuning] {tuning}")
+    ctx = _ctx(c, "c64")
+    for k, v in tuning.items():
+        ctx.tune(k, v)
+    R = inputs.random_complex((5, 4096), 35)
+    Rt = torch.tensor(R, dtype=torch.complex64, device="cuda")
+    for adj in (False, True):
+        Y = ctx.matvec(Rt, adjoint=adj).cpu().numpy()
+        ref = (A.conj().T if adj else A) @ R.T
+        err = _rel(Y, ref.T)
+        y1 = ctx.matvec(Rt[2].contiguous(), adjoint=adj).cpu().numpy()
+        _say(f"  matvec adjoint={adj} rel err {err:.3e}")
+        assert err < 5e-6 and _rel(y1, Y[2]) < 1e-5
+        Z = ctx.precond(Rt, adjoint=adj).cpu().numpy()
+        refz = np.stack([efie.precond_block_apply(A, R[i], 64, adjoint=adj) for i in range(5)])
+        errz = _rel(Z, refz)
+        z1 = ctx.precond(Rt[2].contiguous(), adjoint=adj).cpu().numpy()
+        _say(f"  precond adjoint={adj} rel err {errz:.3e}")
+        assert errz < 5e-5 and _rel(z1, Z[2]) < 1e-5
+    ctx.close()
+
+
 def test_nrhs_beyond_max_is_rejected(torch, spiral):
     from paper_1901_11371_amd._capi import HBF_EINVAL, HbfError
     c, _ = spiral
