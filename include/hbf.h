@@ -169,7 +169,7 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
 /* Set an execution parameter of the context (used by the autotuner; results
  * do not depend on them beyond rounding):
  *   "prog_levels"   subtrees of <= 2^value leaves are swept by one workgroup
- *                   program (0..12; default 6),
+ *                   program (0..12; default 5),
  *   "pipe_max_r"    stage launches with nrhs <= value use pipelined wave teams
  *                   (default 4),
  *   "prog_pipe"     1 = pipelined wave teams inside the sweep programs,

@@ -521,7 +521,8 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
         }
     }
     const int64_t fac_entries = P.leaf_fac_begin + P.leaf_fac_len;
-    dmalloc(&c->d_fac, static_cast<size_t>(fac_entries) * c->elt, "factors");
+    // 16 spare entries: the sweep programs' L2 prefetch touches whole 16-entry granules
+    dmalloc(&c->d_fac, static_cast<size_t>(fac_entries + 16) * c->elt, "factors");
     upload_factors(c.get(), 0, P.leaf_fac_begin, s);
     dmalloc(&c->d_perm, P.perm.size() + 16, "perm");
     if (!P.perm.empty())

@@ -59,6 +59,11 @@ struct alignas(16) Unit {
 };
 static_assert(sizeof(Unit) == 64, "Unit must be 64 bytes");
 
+// Program step table entries: first unit, end unit, flags (1 accumulate,
+// 2 forward mode), first 16-entry granule of the step's matrices and the
+// number of granules they span.
+constexpr int kStepInts = 5;
+
 // A launch of the stage kernel: a range of groups; a group is a list of units
 // whose outputs cover the same rows and are summed (direct=1: each group is
 // the single unit unit_begin + g).

@@ -2,6 +2,7 @@
 // over the H-IDBF), the FP64 host executor of any schedule, the host leaf
 // factorisation used by the construction checks, and the host-only C ABI.
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -53,9 +54,17 @@ struct SweepGen {
   // emit one ordered step (into a program when `prog` is non-null)
   void emit(int32_t u0, int32_t u1, int acc, int kind, Launch* prog, int force_fwd = 0) {
     if (prog) {
+      int64_t m0 = INT64_MAX, m1 = 0;
+      for (int32_t u = u0; u < u1; ++u) {
+        m0 = std::min<int64_t>(m0, P.units[u].mat);
+        m1 = std::max<int64_t>(m1, P.units[u].mat + P.units[u].mat_len);
+      }
+      if (m1 <= m0) m0 = m1 = 0;
       steps.push_back(u0);
       steps.push_back(u1);
       steps.push_back(acc | (force_fwd << 1));
+      steps.push_back(static_cast<int32_t>(m0 / 16));
+      steps.push_back(static_cast<int32_t>((m1 + 15) / 16 - m0 / 16));
       prog->count += 1;
       bound(*prog, u0, u1);
       return;
@@ -76,7 +85,7 @@ struct SweepGen {
     if (!prog && P.V - dd <= prog_levels) {
       Launch l;
       l.direct = 1;
-      l.first = static_cast<int32_t>(steps.size() / 3);
+      l.first = static_cast<int32_t>(steps.size() / kStepInts);
       l.count = 0;
       l.max_src = l.max_dst = l.max_mat = 0;
       l.out_leaf = 1;
@@ -266,7 +275,7 @@ int64_t schedule_bytes(const Plan& P, const std::vector<Launch>& launches, const
   for (const Launch& L : launches) {
     if (L.prog) {
       for (int st = L.first; st < L.first + L.count; ++st)
-        for (int32_t q = (*steps)[3 * st]; q < (*steps)[3 * st + 1]; ++q) add(q);
+        for (int32_t q = (*steps)[kStepInts * st]; q < (*steps)[kStepInts * st + 1]; ++q) add(q);
     } else if (L.direct) {
       for (int32_t q = L.first; q < L.first + L.count; ++q) add(q);
     } else {
@@ -289,10 +298,10 @@ void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cpl
         Launch l = L0;
         l.prog = 0;
         l.direct = 1;
-        l.first = (*steps)[3 * st];
-        l.count = (*steps)[3 * st + 1] - (*steps)[3 * st];
-        l.out_leaf = (*steps)[3 * st + 2] & 1;
-        l.force_fwd = ((*steps)[3 * st + 2] >> 1) & 1;
+        l.first = (*steps)[kStepInts * st];
+        l.count = (*steps)[kStepInts * st + 1] - (*steps)[kStepInts * st];
+        l.out_leaf = (*steps)[kStepInts * st + 2] & 1;
+        l.force_fwd = ((*steps)[kStepInts * st + 2] >> 1) & 1;
         expanded.push_back(l);
       }
     } else {

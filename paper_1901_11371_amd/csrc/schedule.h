@@ -12,11 +12,11 @@ struct Sweeps {
   std::vector<Launch> fwd, bwd;          // P^{-1}: lower then upper substitution
   std::vector<Launch> adj_fwd, adj_bwd;  // P^{-H}
   std::vector<Launch> diag;              // s = D t (block reading, between the sweeps)
-  std::vector<int32_t> steps;            // program steps: (first unit, end unit, flags: 1 accumulate, 2 forward mode)
-  int prog_levels = 6;                   // subtrees of <= 2^prog_levels leaves run as one program
+  std::vector<int32_t> steps;            // program steps, kStepInts entries each
+  int prog_levels = 5;                   // subtrees of <= 2^prog_levels leaves run as one program
 };
 
-void build_sweeps(const Plan& P, Sweeps& S, int prog_levels = 6);
+void build_sweeps(const Plan& P, Sweeps& S, int prog_levels = 5);
 
 // Run a schedule on host buffers in the internal (rows, R) layout.  In
 // adjoint mode every unit reads its forward output segments and writes its

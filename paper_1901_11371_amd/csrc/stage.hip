@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kProgThreads) k_program(StageArgs a, const int
   const int chunk = blockIdx.x;
   const double are = a.alpha_re, aim = a.alpha_im;
   for (int st = s0; st < s1; ++st) {
-    const int u0 = steps[3 * st], u1 = steps[3 * st + 1], flags = steps[3 * st + 2];
+    const int u0 = steps[kStepInts * st], u1 = steps[kStepInts * st + 1], flags = steps[kStepInts * st + 2];
     const int acc = flags & 1;
     const bool fwd_mode = (flags >> 1) & 1;
     StageArgs b = a;

@@ -20,8 +20,12 @@ constexpr int kChunkW = 64 * kPW;       // words per chunk (4 KB)
 constexpr int kSrcPL = 4;               // source entries per lane (256 max)
 constexpr int kPermPL = 8;              // permutation bytes per lane (512 max)
 constexpr int kOpt = 4;                 // outputs per lane (256 max)
-constexpr int kStepWin = 256;           // program steps staged in LDS at a time
+constexpr int kStepWin = 128;           // program steps staged in LDS at a time
 constexpr int kDescMax = 64;            // unit descriptors per program step staged in LDS
+constexpr int kPrefDist = 3;            // program steps the prefetch wave may run ahead
+constexpr int kPrefSlots = 32;          // 128-byte lines per prefetch-wave lane and step
+constexpr int kLook = kPrefDist > 2 ? kPrefDist : 2;  // steps read ahead of the current one
+constexpr int kCompute = kProgWaves - 1;              // waves of a program that take units
 
 template <class T>
 __device__ __forceinline__ void cmac(cx<T>& acc, cx<T> a, cx<T> b) {
@@ -417,31 +421,115 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
 }
 
 // A sweep program run by one workgroup per RHS chunk: steps in order, each a
-// range of independent units shared by the waves (unit u0 + wave + kProgWaves i).
-// The step table is staged in LDS in windows of kStepWin steps, and the
-// descriptors of the first kDescMax units of each step in a ring of three
-// step buffers, loaded two steps ahead.  A wave prefetches one item ahead:
-// the next chunk, its next unit of the same step, or its first unit of the
-// next step (also when it has nothing to do in the current one); the
-// permutations and matrix chunk of that item are requested before the step
-// barrier (they do not depend on the sweep), its sources only after.
+// range of independent units shared by the compute waves (unit
+// u0 + wave + kCompute i).  The step table is staged in LDS in windows of
+// kStepWin steps.  The last wave of the workgroup takes no units: it loads the
+// descriptors of the first kDescMax units of step st + 2 into a ring of three
+// LDS step buffers, and touches one dword of every 128-byte line of the
+// matrices of the next kPrefDist steps so that they are in L2 when the compute
+// waves ask for them (a wave's wait for its own operands would otherwise also
+// wait for these loads).  A compute wave prefetches one item ahead: the next
+// chunk, its next unit of the same step, or its first unit of the next step
+// (also when it has nothing to do in the current one); the permutations and
+// matrix chunk of that item are requested before the step barrier (they do
+// not depend on the sweep), its sources only after.
 template <class F, class V, class A, bool ADJ>
 __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave, int lane,
                          unsigned char* lds, int32_t* s_steps, Unit* ring, int R, int r0, int nr) {
+  const int tid = threadIdx.x;
+  int w0 = s0;  // first step of the staged window
+  auto load_window = [&](int from) {
+    const int cnt = kStepInts * min(kStepWin, s1 - from);
+    for (int e = tid; e < cnt; e += blockDim.x) s_steps[e] = steps[kStepInts * from + e];
+  };
+  auto st_u0 = [&](int st) { return uni(s_steps[kStepInts * (st - w0)]); };
+  auto st_u1 = [&](int st) { return uni(s_steps[kStepInts * (st - w0) + 1]); };
+  auto st_fl = [&](int st) { return uni(s_steps[kStepInts * (st - w0) + 2]); };
+  auto st_g0 = [&](int st) { return uni(s_steps[kStepInts * (st - w0) + 3]); };
+  auto st_ng = [&](int st) { return uni(s_steps[kStepInts * (st - w0) + 4]); };
+  // window reload before step st: every wave has passed the previous step's
+  // barrier, so no reads of the old window remain (uniform over the workgroup)
+  auto maybe_reload = [&](int st) {
+    if (st + kLook >= w0 + kStepWin && st + kLook < s1) {
+      w0 = st;
+      load_window(st);
+      __syncthreads();
+    }
+  };
+  load_window(s0);
+  __syncthreads();
+  {  // ring slots of the first two steps
+    for (int st = s0; st < min(s1, s0 + 2); ++st) {
+      const int b0 = st_u0(st), nu = min(kDescMax, st_u1(st) - b0);
+      if (tid < 4 * nu)
+        reinterpret_cast<u32x4*>(ring + (st % 3) * kDescMax + (tid >> 2))[tid & 3] =
+            reinterpret_cast<const u32x4*>(a.units + b0 + (tid >> 2))[tid & 3];
+    }
+  }
+  __syncthreads();
+
+  if (wave == kCompute) {
+    // ---------------- prefetch wave ----------------
+    constexpr int kLine = 128;
+    const int64_t gbytes = 16 * static_cast<int64_t>(sizeof(cx<F>));
+    const char* fac = reinterpret_cast<const char*>(a.fac);
+    unsigned sink = 0;
+    int pst = s0 + 1, pdone = 0;  // cursor: step and lines of it already touched
+    for (int st = s0; st < s1; ++st) {
+      maybe_reload(st);
+      u32x4 rv[4];
+      int rcount = 0;
+      if (st + 2 < s1) {
+        const int b0 = st_u0(st + 2), nu = min(kDescMax, st_u1(st + 2) - b0);
+        rcount = nu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int e = lane + 64 * j;
+          if (e < 4 * nu) rv[j] = reinterpret_cast<const u32x4*>(a.units + b0 + (e >> 2))[e & 3];
+        }
+      }
+      if (pst <= st) {
+        pst = st + 1;
+        pdone = 0;
+      }
+      const int lim = min(s1 - 1, st + kPrefDist);
+      int nl = pst <= lim ? static_cast<int>(st_ng(pst) * gbytes / kLine) : 0;
+      int pv[kPrefSlots];
+#pragma unroll
+      for (int j = 0; j < kPrefSlots; ++j) {
+        while (pst <= lim && pdone >= nl) {
+          ++pst;
+          pdone = 0;
+          nl = pst <= lim ? static_cast<int>(st_ng(pst) * gbytes / kLine) : 0;
+        }
+        pv[j] = 0;
+        if (pst <= lim) {
+          const int line = pdone + lane;
+          if (line < nl)
+            pv[j] = *reinterpret_cast<const int*>(fac + st_g0(pst) * gbytes + static_cast<int64_t>(line) * kLine);
+          pdone += 64;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = lane + 64 * j;
+        if (e < 4 * rcount)
+          reinterpret_cast<u32x4*>(ring + ((st + 2) % 3) * kDescMax + (e >> 2))[e & 3] = rv[j];
+      }
+#pragma unroll
+      for (int j = 0; j < kPrefSlots; ++j) sink ^= static_cast<unsigned>(pv[j]);
+      __syncthreads();
+    }
+    if (a.R < 0) reinterpret_cast<unsigned*>(a.buf[BUF_X])[tid] = sink;  // never taken (R >= 1): keeps the loads
+    return;
+  }
+
+  // ---------------- compute waves ----------------
   cx<A>* s_src = reinterpret_cast<cx<A>*>(lds);
   uint8_t* s_p = reinterpret_cast<uint8_t*>(s_src + 256);
   uint8_t* s_q = s_p + 512;
   u32x4* s_m4 = reinterpret_cast<u32x4*>(s_q + 512);
   const cx<F>* s_mat = reinterpret_cast<const cx<F>*>(s_m4);
-  const int tid = threadIdx.x;
-  int w0 = s0;  // first step of the staged window
-  auto load_window = [&](int from) {
-    const int cnt = 3 * min(kStepWin, s1 - from);
-    for (int e = tid; e < cnt; e += blockDim.x) s_steps[e] = steps[3 * from + e];
-  };
-  auto st_u0 = [&](int st) { return uni(s_steps[3 * (st - w0)]); };
-  auto st_u1 = [&](int st) { return uni(s_steps[3 * (st - w0) + 1]); };
-  auto st_fl = [&](int st) { return uni(s_steps[3 * (st - w0) + 2]); };
   // descriptor of unit q of step st, in the orientation the step applies it in
   auto desc_at = [&](int q, int st) -> UDesc {
     const int i = q - st_u0(st);
@@ -452,23 +540,6 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
     if (ADJ && ((fl >> 1) & 1)) return read_desc<false, F>(&u);
     return read_desc<ADJ, F>(&u);
   };
-  // ring slot of step st <- descriptors of its first kDescMax units (16 bytes per thread)
-  auto ring_src = [&](int st, u32x4& v) -> bool {
-    const int b0 = st_u0(st), nu = min(kDescMax, st_u1(st) - b0);
-    if (tid >= 4 * nu) return false;
-    v = reinterpret_cast<const u32x4*>(a.units + b0 + (tid >> 2))[tid & 3];
-    return true;
-  };
-  auto ring_put = [&](int st, const u32x4& v) {
-    reinterpret_cast<u32x4*>(ring + (st % 3) * kDescMax + (tid >> 2))[tid & 3] = v;
-  };
-  load_window(s0);
-  __syncthreads();
-  for (int st = s0; st < min(s1, s0 + 2); ++st) {
-    u32x4 v;
-    if (ring_src(st, v)) ring_put(st, v);
-  }
-  __syncthreads();
   bool have = false;       // the item (cq, cc) of step cst has been requested
   bool src_ready = false;  // ... including its sources
   int cq = 0, cc = 0, cst = s0;
@@ -478,14 +549,7 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
 #pragma unroll
   for (int j = 0; j < kOpt; ++j) acc[j] = cx<A>{0, 0};
   for (int st = s0; st < s1; ++st) {
-    if (st + 2 >= w0 + kStepWin && st + 2 < s1) {
-      // every wave has passed the previous step's barrier: no reads of the old window remain
-      w0 = st;
-      load_window(st);
-      __syncthreads();
-    }
-    u32x4 rv;
-    const bool rload = (st + 2 < s1) && ring_src(st + 2, rv);
+    maybe_reload(st);
     const int u0 = st_u0(st), u1 = st_u1(st), flags = st_fl(st);
     if (!have && u0 + wave < u1) {
       cq = u0 + wave;
@@ -508,8 +572,8 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
       if (nc >= nch) {
         unit_end = true;
         nc = 0;
-        if (cq + kProgWaves < u1) {
-          nq = cq + kProgWaves;
+        if (cq + kCompute < u1) {
+          nq = cq + kCompute;
         } else if (st + 1 < s1 && st_u0(st + 1) + wave < st_u1(st + 1)) {
           nq = st_u0(st + 1) + wave;
           nst = st + 1;
@@ -551,7 +615,6 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
       have = true;
       src_ready = false;
     }
-    if (rload) ring_put(st + 2, rv);
     __syncthreads();
   }
 }
@@ -613,7 +676,7 @@ static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int
   const int lds1 = pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
   const dim3 grid(static_cast<unsigned>(a.nchunks));
   const size_t lds =
-      static_cast<size_t>(lds1) * kProgWaves + 3 * kDescMax * sizeof(Unit) + 3 * sizeof(int32_t) * kStepWin;
+      static_cast<size_t>(lds1) * kProgWaves + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin;
   if (adjoint)
     hipLaunchKernelGGL((k_program_pipe<F, V, A, true>), grid, dim3(64 * kProgWaves), lds, s, a, steps, s0, s1, lds1);
   else

@@ -149,3 +149,18 @@ def test_rank_statistics_and_storage():
     assert 4 < st["mean_rank"] < 40 and st["max_rank"] <= 127
     # compressed storage well below the dense N^2 entries
     assert st["bytes_butterfly"] + st["bytes_dense"] < 0.3 * 16 * 8192 ** 2
+
+
+def test_storage_scales_as_n_log2_squared():
+    """Memory O(N log^2 N) (abstract and Sec. 4): the stored factor bytes of the
+    semicircle over N = 2^12 ... 2^15 divided by N log2(N)^2 stay within a
+    narrow band, while bytes / N^1.5 falls steadily."""
+    ratios, dense_ratios = [], []
+    for e in range(12, 16):
+        n = 1 << e
+        st = _plan(inputs.semicircle(n)).stats
+        b = st["bytes_butterfly"] + st["bytes_dense"]
+        ratios.append(b / (n * e * e))
+        dense_ratios.append(b / n ** 1.5)
+    assert max(ratios) / min(ratios) < 1.6, ratios
+    assert all(dense_ratios[i + 1] < dense_ratios[i] for i in range(len(dense_ratios) - 1)), dense_ratios
