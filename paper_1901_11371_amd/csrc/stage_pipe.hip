@@ -52,6 +52,12 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Buffer i of the launch, selected by uniform branches (no runtime index into
+// the argument array).
+__device__ __forceinline__ void* bufp(const StageArgs& a, int i) {
+  return i == BUF_X ? a.buf[BUF_X] : (i == BUF_Y ? a.buf[BUF_Y] : a.buf[BUF_ARENA]);
+}
+
 // Unit fields a team needs, in the team's own orientation (source/destination).
 struct UDesc {
   int64_t mat, perm;
@@ -128,11 +134,12 @@ __device__ __forceinline__ void issue_static(const StageArgs& a, const UDesc& d,
     const int w = c * kChunkW + lane + 64 * j;
     if (w < d.nwords) s.mw[j] = __builtin_nontemporal_load(&gm[w]);
   }
-  if (c == 0) {
+  if (c == 0 && d.plen > 0) {
+    const uint8_t* pp = a.perm + d.perm;
 #pragma unroll
     for (int j = 0; j < kPermPL; ++j) {
       const int e = lane + 64 * j;
-      if (e < 2 * d.plen) s.pv[j] = a.perm[d.perm + e];
+      if (e < 2 * d.plen) s.pv[j] = pp[e];
     }
   }
 }
@@ -140,7 +147,7 @@ __device__ __forceinline__ void issue_static(const StageArgs& a, const UDesc& d,
 template <class F, class V, class A, bool ADJ>
 __device__ __forceinline__ void issue_src(const StageArgs& a, const UDesc& d, int lane, int R, int r0, int nr,
                                           Slot<V>& s) {
-  const V* sb = reinterpret_cast<const V*>(a.buf[d.s_buf]);
+  const V* sb = reinterpret_cast<const V*>(bufp(a, d.s_buf));
 #pragma unroll
   for (int j = 0; j < kSrcPL; ++j) {
     const int e = lane + 64 * j;
@@ -315,7 +322,7 @@ template <class V, class A>
 __device__ __forceinline__ void write_dst(const StageArgs& a, const UDesc& d, int acc_mode, double alpha_re,
                                           double alpha_im, int lane, int R, int r0, int nr, cx<A>* acc,
                                           bool split) {
-  V* db = reinterpret_cast<V*>(a.buf[d.d_buf]);
+  V* db = reinterpret_cast<V*>(bufp(a, d.d_buf));
   const A are = static_cast<A>(alpha_re), aim = static_cast<A>(alpha_im);
   const int P = lanes_per_output(d.n_dst * nr, split);
   if (P > 1) {
@@ -646,8 +653,8 @@ __global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, c
   const int nr = min(a.rc, a.R - r0);
   Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(kProgWaves) * team_lds);
   int32_t* s_steps = reinterpret_cast<int32_t*>(ring + 3 * kDescMax);
-  prog_run<F, V, A, ADJ>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps, ring,
-                         a.R, r0, nr);
+  prog_run<F, V, A, ADJ>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
+                         ring, a.R, r0, nr);
 }
 
 }  // namespace
