@@ -60,7 +60,8 @@ struct alignas(16) Unit {
 static_assert(sizeof(Unit) == 64, "Unit must be 64 bytes");
 
 // Program step table entries: first unit, end unit, flags (1 accumulate,
-// 2 forward mode), first 16-entry granule of the step's matrices and the
+// 2 forward mode, 4 all units are dense 8-row slabs with one input and one
+// output segment), first 16-entry granule of the step's matrices and the
 // number of granules they span.
 constexpr int kStepInts = 5;
 

@@ -60,9 +60,17 @@ struct SweepGen {
         m1 = std::max<int64_t>(m1, P.units[u].mat + P.units[u].mat_len);
       }
       if (m1 <= m0) m0 = m1 = 0;
+      // flag 4: every unit is a dense 8-row slab read from one input segment
+      // and written (not accumulated) to one output segment
+      bool slab = acc == 0 && u1 > u0;
+      for (int32_t u = u0; u < u1 && slab; ++u) {
+        const Unit& q = P.units[u];
+        slab = q.type == UNIT_DENSE && q.out_len[0] == 8 && q.out_len[1] == 0 && q.in_len[1] == 0 &&
+               q.in_len[0] % 64 == 0 && q.in_len[0] > 0;
+      }
       steps.push_back(u0);
       steps.push_back(u1);
-      steps.push_back(acc | (force_fwd << 1));
+      steps.push_back(acc | (force_fwd << 1) | (slab ? 4 : 0));
       steps.push_back(static_cast<int32_t>(m0 / 16));
       steps.push_back(static_cast<int32_t>((m1 + 15) / 16 - m0 / 16));
       prog->count += 1;

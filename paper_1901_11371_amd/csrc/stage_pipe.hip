@@ -198,11 +198,11 @@ __device__ __forceinline__ void commit(const UDesc& d, int c, int lane, int nr, 
 // output's dot product (each takes every P-th term); write_dst reduces them.
 // Only for items that are written on their own (`split`): the units of a
 // group accumulate into the same registers and must agree on the mapping.
-__device__ __forceinline__ int lanes_per_output(int nout, bool split) {
-  int P = 1;
+__device__ __forceinline__ int lanes_per_output_log2(int nout, bool split) {
+  int lp = 0;
   if (split)
-    while (P < 32 && nout * P * 2 <= 64) P *= 2;
-  return P;
+    while (lp < 5 && (nout << (lp + 1)) <= 64) ++lp;
+  return lp;
 }
 
 template <class F, class A, bool ADJ>
@@ -214,12 +214,14 @@ __device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, in
   const int e1 = min(d.mat_len, e0 + kChunkE);
   const int type = d.type;
   const int k0 = d.k0, k1 = d.k1, f_in = d.f_in, f_out = d.f_out;
-  const int P = lanes_per_output(d.n_dst * nr, split);
+  const int lp = lanes_per_output_log2(d.n_dst * nr, split);
+  const int P = 1 << lp;
   const int part = lane & (P - 1);
   const bool first_chunk = (c == 0) && part == 0;
+  const bool whole = (c == 0) && d.mat_len <= kChunkE;  // the item holds all of the unit's matrices
 #pragma unroll
   for (int j = 0; j < kOpt; ++j) {
-    const int p = (P > 1) ? (lane / P) : lane + 64 * j;
+    const int p = (P > 1) ? (lane >> lp) : lane + 64 * j;
     if (P > 1 && j > 0) break;
     if (p >= d.n_dst * nr) break;
     const int o = p / nr;
@@ -233,7 +235,11 @@ __device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, in
     };
     if (type == UNIT_DENSE) {
       if (!ADJ) {
-        const int tlo = cdiv_pos(e0 - o, f_out), thi = min(f_in, cdiv_pos(e1 - o, f_out));
+        int tlo = 0, thi = f_in;
+        if (!whole) {
+          tlo = cdiv_pos(e0 - o, f_out);
+          thi = min(f_in, cdiv_pos(e1 - o, f_out));
+        }
         for (int t = tlo + part; t < thi; t += P) MAC(t * f_out + o, t);
       } else {
         const int base = o * f_out;
@@ -253,7 +259,11 @@ __device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, in
           s.x += v.x;
           s.y += v.y;
         }
-        const int tlo = cdiv_pos(e0 - base - i, k), thi = min(r, cdiv_pos(e1 - base - i, k));
+        int tlo = 0, thi = r;
+        if (!whole) {
+          tlo = cdiv_pos(e0 - base - i, k);
+          thi = min(r, cdiv_pos(e1 - base - i, k));
+        }
         for (int t = tlo + part; t < thi; t += P) MAC(base + t * k + i, pm[k + t]);
       } else {
 #pragma unroll
@@ -292,7 +302,11 @@ __device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, in
             }
           } else {
             const int t = qq - k;
-            const int jlo = cdiv_pos(e0 - base - t, r), jhi = min(k, cdiv_pos(e1 - base - t, r));
+            int jlo = 0, jhi = k;
+            if (!whole) {
+              jlo = cdiv_pos(e0 - base - t, r);
+              jhi = min(k, cdiv_pos(e1 - base - t, r));
+            }
             for (int jj = jlo + part; jj < jhi; jj += P) MAC(base + jj * r + t, sbase + jj);
           }
         }
@@ -324,7 +338,8 @@ __device__ __forceinline__ void write_dst(const StageArgs& a, const UDesc& d, in
                                           bool split) {
   V* db = reinterpret_cast<V*>(bufp(a, d.d_buf));
   const A are = static_cast<A>(alpha_re), aim = static_cast<A>(alpha_im);
-  const int P = lanes_per_output(d.n_dst * nr, split);
+  const int lp = lanes_per_output_log2(d.n_dst * nr, split);
+  const int P = 1 << lp;
   if (P > 1) {
     for (int off = P / 2; off >= 1; off /= 2) {
       acc[0].x += __shfl_xor(acc[0].x, off);
@@ -333,7 +348,7 @@ __device__ __forceinline__ void write_dst(const StageArgs& a, const UDesc& d, in
   }
 #pragma unroll
   for (int j = 0; j < kOpt; ++j) {
-    const int p = (P > 1) ? (lane / P) : lane + 64 * j;
+    const int p = (P > 1) ? (lane >> lp) : lane + 64 * j;
     if (P > 1 && (j > 0 || (lane & (P - 1)) != 0)) {
       acc[j] = cx<A>{0, 0};
       continue;
@@ -427,6 +442,67 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
   }
 }
 
+// A dense 8-row slab unit (column-major 8 x w matrix, one input and one
+// output segment, one RHS), forward: the wave streams the matrix straight into
+// registers with coalesced 16-byte loads (lane l, load k: word l + 64 k, so a
+// wave instruction reads one contiguous kilobyte), together with the matching
+// input entries; lanes holding the same rows reduce by shuffles.
+template <class F, class V, class A>
+__device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, int lane, int R, int r0) {
+  constexpr int EP = 16 / static_cast<int>(sizeof(cx<F>));  // complex entries per 16-byte word
+  constexpr int G = 8 / EP;                                  // words per column
+  constexpr int B = 4;                                       // words in flight per lane
+  const u32x4* gm = reinterpret_cast<const u32x4*>(reinterpret_cast<const cx<F>*>(a.fac) + d.mat);
+  const V* xb = reinterpret_cast<const V*>(bufp(a, d.s_buf));
+  const int nw = d.n_src * G;
+  cx<A> acc[EP];
+#pragma unroll
+  for (int q = 0; q < EP; ++q) acc[q] = cx<A>{0, 0};
+  for (int k0 = 0; k0 < nw; k0 += 64 * B) {
+    u32x4 m[B];
+    V xv[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int wi = k0 + 64 * b + lane;
+      if (wi < nw) {
+        m[b] = __builtin_nontemporal_load(&gm[wi]);
+        xv[b] = xb[static_cast<int64_t>(d.s_off0 + wi / G) * R + r0];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int wi = k0 + 64 * b + lane;
+      if (wi < nw) {
+        const cx<A> x = up<A>(xv[b]);
+        if constexpr (EP == 2) {
+          cmac(acc[0], cx<A>{__uint_as_float(m[b][0]), __uint_as_float(m[b][1])}, x);
+          cmac(acc[1], cx<A>{__uint_as_float(m[b][2]), __uint_as_float(m[b][3])}, x);
+        } else {
+          const double re = __hiloint2double(static_cast<int>(m[b][1]), static_cast<int>(m[b][0]));
+          const double im = __hiloint2double(static_cast<int>(m[b][3]), static_cast<int>(m[b][2]));
+          cmac(acc[0], cx<A>{static_cast<A>(re), static_cast<A>(im)}, x);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+    for (int q = 0; q < EP; ++q) {
+      acc[q].x += __shfl_xor(acc[q].x, off);
+      acc[q].y += __shfl_xor(acc[q].y, off);
+    }
+  }
+  if (lane < G) {
+    V* db = reinterpret_cast<V*>(bufp(a, d.d_buf));
+    using VT = decltype(db->x);
+#pragma unroll
+    for (int q = 0; q < EP; ++q)
+      db[static_cast<int64_t>(d.d_off0 + EP * lane + q) * R + r0] =
+          V{static_cast<VT>(acc[q].x), static_cast<VT>(acc[q].y)};
+  }
+}
+
 // A sweep program run by one workgroup per RHS chunk: steps in order, each a
 // range of independent units shared by the compute waves (unit
 // u0 + wave + kCompute i).  The step table is staged in LDS in windows of
@@ -440,7 +516,7 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
 // (also when it has nothing to do in the current one); the permutations and
 // matrix chunk of that item are requested before the step barrier (they do
 // not depend on the sweep), its sources only after.
-template <class F, class V, class A, bool ADJ>
+template <class F, class V, class A, bool ADJ, bool NR1>
 __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave, int lane,
                          unsigned char* lds, int32_t* s_steps, Unit* ring, int R, int r0, int nr) {
   const int tid = threadIdx.x;
@@ -555,10 +631,14 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
   cx<A> acc[kOpt];
 #pragma unroll
   for (int j = 0; j < kOpt; ++j) acc[j] = cx<A>{0, 0};
+  // slab steps (one RHS) run through slab_unit and take no lookahead item
+  auto is_slab = [&](int st) { return NR1 && ((st_fl(st) >> 2) & 1); };
   for (int st = s0; st < s1; ++st) {
     maybe_reload(st);
     const int u0 = st_u0(st), u1 = st_u1(st), flags = st_fl(st);
-    if (!have && u0 + wave < u1) {
+    if (is_slab(st)) {
+      for (int q = u0 + wave; q < u1; q += kCompute) slab_unit<F, V, A>(a, desc_at(q, st), lane, R, r0);
+    } else if (!have && u0 + wave < u1) {
       cq = u0 + wave;
       cc = 0;
       cst = st;
@@ -581,7 +661,7 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
         nc = 0;
         if (cq + kCompute < u1) {
           nq = cq + kCompute;
-        } else if (st + 1 < s1 && st_u0(st + 1) + wave < st_u1(st + 1)) {
+        } else if (st + 1 < s1 && !is_slab(st + 1) && st_u0(st + 1) + wave < st_u1(st + 1)) {
           nq = st_u0(st + 1) + wave;
           nst = st + 1;
         } else {
@@ -613,7 +693,7 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
       d = dn;
     }
     // a wave without work in this step requests its first item of the next one
-    if (!have && st + 1 < s1 && st_u0(st + 1) + wave < st_u1(st + 1)) {
+    if (!have && st + 1 < s1 && !is_slab(st + 1) && st_u0(st + 1) + wave < st_u1(st + 1)) {
       cq = st_u0(st + 1) + wave;
       cc = 0;
       cst = st + 1;
@@ -627,14 +707,15 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
 }
 
 // Stage launch: teams = waves; team t handles groups t, t + nteams, ... for RHS chunk `chunk`.
-template <class F, class V, class A, bool ADJ>
+// NR1: every RHS chunk holds one right-hand side (nr == 1 at compile time).
+template <class F, class V, class A, bool ADJ, bool NR1>
 __global__ void __launch_bounds__(256) k_stage_pipe(StageArgs a, int ngroups, int team_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int chunk = blockIdx.y;
   const int r0 = chunk * a.rc;
-  const int nr = min(a.rc, a.R - r0);
+  const int nr = NR1 ? 1 : min(a.rc, a.R - r0);
   const int team = blockIdx.x * 4 + wave;
   const int nteams = gridDim.x * 4;
   team_run<F, V, A, ADJ>(a, a.first, ngroups, team, nteams, lane, smem + static_cast<size_t>(wave) * team_lds, a.R,
@@ -642,7 +723,7 @@ __global__ void __launch_bounds__(256) k_stage_pipe(StageArgs a, int ngroups, in
 }
 
 // Sweep program kernel: one workgroup per RHS chunk.
-template <class F, class V, class A, bool ADJ>
+template <class F, class V, class A, bool ADJ, bool NR1>
 __global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, const int32_t* steps, int s0, int s1,
                                                                   int team_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -650,10 +731,10 @@ __global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, c
   const int lane = threadIdx.x & 63;
   const int chunk = blockIdx.x;
   const int r0 = chunk * a.rc;
-  const int nr = min(a.rc, a.R - r0);
+  const int nr = NR1 ? 1 : min(a.rc, a.R - r0);
   Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(kProgWaves) * team_lds);
   int32_t* s_steps = reinterpret_cast<int32_t*>(ring + 3 * kDescMax);
-  prog_run<F, V, A, ADJ>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
+  prog_run<F, V, A, ADJ, NR1>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
                          ring, a.R, r0, nr);
 }
 
@@ -672,8 +753,15 @@ static hipError_t launch_pipe(const StageArgs& a, int ngroups, int nchunks, bool
   if (bx > max_blocks) bx = max_blocks;
   if (bx < 1) bx = 1;
   const dim3 grid(static_cast<unsigned>(bx), static_cast<unsigned>(nchunks));
-  if (adjoint) hipLaunchKernelGGL((k_stage_pipe<F, V, A, true>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
-  else hipLaunchKernelGGL((k_stage_pipe<F, V, A, false>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
+  const bool nr1 = a.rc == 1;
+  if (adjoint && nr1)
+    hipLaunchKernelGGL((k_stage_pipe<F, V, A, true, true>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
+  else if (adjoint)
+    hipLaunchKernelGGL((k_stage_pipe<F, V, A, true, false>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
+  else if (nr1)
+    hipLaunchKernelGGL((k_stage_pipe<F, V, A, false, true>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
+  else
+    hipLaunchKernelGGL((k_stage_pipe<F, V, A, false, false>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
   return hipGetLastError();
 }
 
@@ -684,10 +772,16 @@ static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int
   const dim3 grid(static_cast<unsigned>(a.nchunks));
   const size_t lds =
       static_cast<size_t>(lds1) * kProgWaves + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin;
-  if (adjoint)
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, true>), grid, dim3(64 * kProgWaves), lds, s, a, steps, s0, s1, lds1);
+  const dim3 block(64 * kProgWaves);
+  const bool nr1 = a.rc == 1;
+  if (adjoint && nr1)
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
+  else if (adjoint)
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
+  else if (nr1)
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
   else
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, false>), grid, dim3(64 * kProgWaves), lds, s, a, steps, s0, s1, lds1);
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
   return hipGetLastError();
 }
 
