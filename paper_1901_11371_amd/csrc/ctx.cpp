@@ -305,6 +305,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.src_cap = 0;
       a.ch = 0;
       a.split = c->lane_split ? 1 : 0;
+      a.single = l.single;
       hipError_t e;
       if (c->dtype == HBF_C128) e = launch_pipe_c128(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
       else if (vec_c128) e = launch_pipe_c64_hi(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);

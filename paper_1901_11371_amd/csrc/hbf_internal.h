@@ -79,6 +79,7 @@ struct Launch {
   int32_t kind;        // 0 butterfly/dense, 1 leaf solve
   int32_t prog = 0;    // 1: a sequential program over steps [first, first+count) of the step table
   int32_t force_fwd = 0;  // 1: apply the units in forward mode even in an adjoint schedule
+  int32_t single = 1;     // 1: every group is one unit (no accumulation across units)
 };
 
 // Per-butterfly-block bookkeeping.

@@ -31,6 +31,7 @@ struct StageArgs {
   int32_t ch;             // matrix chunk capacity (entries) in LDS
   int32_t src_cap;        // LDS source capacity (rows x rc entries)
   int32_t split = 1;      // 1: up to 32 lanes may share one output of a small unit (pipelined kernels)
+  int32_t single = 0;     // 1: every group is one unit (lanes may then share an output)
 };
 
 constexpr int kStageThreads = 256;

@@ -563,10 +563,12 @@ Launch make_launch(const Plan& P, int direct, int first, int count, int acc, int
     l.max_dst = std::max({l.max_dst, a, b});
     l.max_mat = std::max<int32_t>(l.max_mat, u.mat_len);
   };
+  l.single = 1;
   for (int g = first; g < first + count; ++g) {
     if (direct) {
       visit(g);
     } else {
+      if (P.group_off[g + 1] - P.group_off[g] != 1) l.single = 0;
       for (int32_t q = P.group_off[g]; q < P.group_off[g + 1]; ++q) visit(P.group_units[q]);
     }
   }

@@ -25,7 +25,12 @@ constexpr int kDescMax = 64;            // unit descriptors per program step sta
 constexpr int kPrefDist = 3;            // program steps the prefetch wave may run ahead
 constexpr int kPrefSlots = 32;          // 128-byte lines per prefetch-wave lane and step
 constexpr int kLook = kPrefDist > 2 ? kPrefDist : 2;  // steps read ahead of the current one
-constexpr int kCompute = kProgWaves - 1;              // waves of a program that take units
+// Waves of a program workgroup: 16 with complex64 factors; 12 with complex128,
+// whose wider registers would otherwise spill at 4 waves per SIMD.
+template <class F>
+constexpr int prog_waves() {
+  return sizeof(F) == 4 ? 16 : 12;
+}
 
 template <class T>
 __device__ __forceinline__ void cmac(cx<T>& acc, cx<T> a, cx<T> b) {
@@ -433,8 +438,9 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
       if (nxt.c == 0) dn = read_desc<ADJ, F>(unit_of(nxt.q));
       issue<F, V, A, ADJ>(a, dn, nxt.c, lane, R, r0, nr, slot);
     }
-    compute_item<F, A, ADJ>(d, cur.c, lane, nr, s_src, s_p, s_q, s_mat, acc, a.direct && a.split);
-    if (group_end) write_dst<V, A>(a, d, a.acc, a.alpha_re, a.alpha_im, lane, R, r0, nr, acc, a.direct && a.split);
+    compute_item<F, A, ADJ>(d, cur.c, lane, nr, s_src, s_p, s_q, s_mat, acc, (a.direct || a.single) && a.split);
+    if (group_end)
+      write_dst<V, A>(a, d, a.acc, a.alpha_re, a.alpha_im, lane, R, r0, nr, acc, (a.direct || a.single) && a.split);
     wsync();
     if (nxt.q < 0) break;
     cur = nxt;
@@ -505,7 +511,7 @@ __device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, in
 
 // A sweep program run by one workgroup per RHS chunk: steps in order, each a
 // range of independent units shared by the compute waves (unit
-// u0 + wave + kCompute i).  The step table is staged in LDS in windows of
+// u0 + wave + kCompute i, kCompute = prog_waves - 1).  The step table is staged in LDS in windows of
 // kStepWin steps.  The last wave of the workgroup takes no units: it loads the
 // descriptors of the first kDescMax units of step st + 2 into a ring of three
 // LDS step buffers, and touches one dword of every 128-byte line of the
@@ -519,6 +525,7 @@ __device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, in
 template <class F, class V, class A, bool ADJ, bool NR1>
 __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave, int lane,
                          unsigned char* lds, int32_t* s_steps, Unit* ring, int R, int r0, int nr) {
+  constexpr int kCompute = prog_waves<F>() - 1;  // waves that take units; the last one prefetches
   const int tid = threadIdx.x;
   int w0 = s0;  // first step of the staged window
   auto load_window = [&](int from) {
@@ -724,7 +731,7 @@ __global__ void __launch_bounds__(256) k_stage_pipe(StageArgs a, int ngroups, in
 
 // Sweep program kernel: one workgroup per RHS chunk.
 template <class F, class V, class A, bool ADJ, bool NR1>
-__global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, const int32_t* steps, int s0, int s1,
+__global__ void __launch_bounds__(64 * prog_waves<F>()) k_program_pipe(StageArgs a, const int32_t* steps, int s0, int s1,
                                                                   int team_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -732,7 +739,7 @@ __global__ void __launch_bounds__(64 * kProgWaves) k_program_pipe(StageArgs a, c
   const int chunk = blockIdx.x;
   const int r0 = chunk * a.rc;
   const int nr = NR1 ? 1 : min(a.rc, a.R - r0);
-  Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(kProgWaves) * team_lds);
+  Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(prog_waves<F>()) * team_lds);
   int32_t* s_steps = reinterpret_cast<int32_t*>(ring + 3 * kDescMax);
   prog_run<F, V, A, ADJ, NR1>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
                          ring, a.R, r0, nr);
@@ -771,8 +778,8 @@ static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int
   const int lds1 = pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
   const dim3 grid(static_cast<unsigned>(a.nchunks));
   const size_t lds =
-      static_cast<size_t>(lds1) * kProgWaves + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin;
-  const dim3 block(64 * kProgWaves);
+      static_cast<size_t>(lds1) * prog_waves<F>() + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin;
+  const dim3 block(64 * prog_waves<F>());
   const bool nr1 = a.rc == 1;
   if (adjoint && nr1)
     hipLaunchKernelGGL((k_program_pipe<F, V, A, true, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
