@@ -56,8 +56,9 @@ def main():
     ap.add_argument("--no-srhs", action="store_true", help="skip the semicircle seconds-per-RHS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond"],
-                    help="matvec / precond: only the single-RHS apply loop (for profiling)")
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch"],
+                    help="matvec / precond: only the single-RHS apply loop; precond_batch: the nrhs-RHS "
+                         "preconditioner loop with the autotuned parameters (for profiling)")
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -115,6 +116,12 @@ def main():
     if args.mode == "matvec":
         print(json.dumps({"mode": "matvec", "ms": t_mv * 1e3, "gbs": (mv_fac + vec1) / t_mv / 1e9,
                           "launches": mv_launches, "avg_launch_us": t_mv / mv_launches * 1e6}))
+        return
+    if args.mode == "precond_batch":
+        autotune.apply(ctx, R) or autotune.autotune(ctx, nrhs=R, reps=1)
+        XB = torch.tensor(inputs.random_complex((R, n), 8), dtype=torch.complex64, device=dev)
+        t_pb = timed_loop(lambda: ctx.precond(XB), max(2, args.reps // 10))
+        print(json.dumps({"mode": "precond_batch", "nrhs": R, "ms": t_pb * 1e3}))
         return
     t_pc = timed_loop(lambda: ctx.precond(x1), max(2, args.reps // 10))
     log(f"[bench] 1-RHS c64 preconditioner {t_pc*1e3:.3f} ms -> {(pc_fac + vec1)/t_pc/1e9:.1f} GB/s")

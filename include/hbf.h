@@ -179,6 +179,10 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *   "wave_units"    1 = one wave per unit for two-RHS stages,
  *   "lane_split"    1 = in the pipelined kernels, up to 32 lanes share the
  *                   dot product of one output of a unit with few outputs,
+ *   "sweep_pipe_max_r"  as pipe_max_r, for the sweeps' stage launches
+ *                   (default 4),
+ *   "sweep_rc1"     1 = the sweeps' stage launches with nrhs > sweep_pipe_max_r
+ *                   use the pipelined kernel with one RHS per workgroup chunk,
  *   "use_graphs"    1 = replay the preconditioner sweeps from HIP graphs.
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);

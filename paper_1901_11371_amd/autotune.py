@@ -8,9 +8,11 @@ fastest:
 * ``prog_levels``: subtrees of at most 2^p leaves are swept inside one
   workgroup program (deep subtrees: fewer launches and cheap step
   barriers, but one workgroup per RHS chunk streams their factors);
-* the stage kernel of the matvec and of the big sweep blocks: the
-  software-pipelined wave teams (``pipe_max_r`` >= nrhs), one unit per wave
-  (``wave_units``), or one unit per workgroup.
+* the stage kernel of the matvec and, separately, of the big sweep blocks:
+  the software-pipelined wave teams (``pipe_max_r`` / ``sweep_pipe_max_r``
+  >= nrhs), or one unit per wave / workgroup (``wave_units``); and whether
+  the sweeps' stage launches use the pipelined kernel with one RHS per chunk
+  (``sweep_rc1``).
 
 Results are cached in a JSON table keyed by (N, nrhs, dtype, preconditioner)
 so later runs of the same shape apply them without timing.
@@ -26,9 +28,11 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib",
 
 # stage-kernel variants: name -> hbf_tune settings
 KERNELS = {
-    "pipe": lambda R: {"pipe_max_r": max(R, 1), "wave_units": 1},
-    "wave": lambda R: {"pipe_max_r": 0, "wave_units": 1},
-    "block": lambda R: {"pipe_max_r": 0, "wave_units": 0},
+    "pipe": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0},
+    "wave": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0},
+    "wave+sweep_pipe": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0},
+    "pipe+sweep_wave": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0},
+    "wave+rc1": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 1},
 }
 
 
@@ -68,7 +72,7 @@ def apply(ctx, nrhs, path=DEFAULT_TABLE):
     return entry
 
 
-def autotune(ctx, nrhs=1, reps=2, prog_levels=(4, 5, 6, 7, 8), kernels=("pipe", "wave"), path=DEFAULT_TABLE,
+def autotune(ctx, nrhs=1, reps=2, prog_levels=(4, 5, 6, 7, 8), kernels=tuple(KERNELS), path=DEFAULT_TABLE,
              verbose=False):
     """Time the candidates on `ctx` (an hbf.Context) and keep the best."""
     dt = torch.complex64 if ctx.dtype == "c64" else torch.complex128

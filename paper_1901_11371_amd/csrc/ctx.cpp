@@ -228,7 +228,7 @@ hbf_status fail(hbf_status st, const std::string& msg) {
 namespace hbf {
 
 hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
-                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s) {
+                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep) {
   const size_t szA = (vec_c128 || c->dtype == HBF_C128) ? 16 : 8;
   const size_t szF = c->elt;
   const int ch_cap = static_cast<int>(32768 / szF);
@@ -295,8 +295,10 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     const int md = std::max(1, l.max_dst);
     const bool adj = adjoint && !l.force_fwd;
     const int mxp = std::max({1, l.max_dst, l.max_src});
-    if (R <= c->pipe_max_r && mxp <= 256) {
-      const int rc = std::min(R, std::max(1, 256 / mxp));
+    const int pmr = sweep ? c->sweep_pipe_max_r : c->pipe_max_r;
+    const bool rc1 = sweep && c->sweep_rc1 && R > pmr;
+    if ((R <= pmr || rc1) && mxp <= 256) {
+      const int rc = rc1 ? 1 : std::min(R, std::max(1, 256 / mxp));
       a.rc = rc;
       a.nchunks = (R + rc - 1) / rc;
       a.acc = l.out_leaf;
@@ -385,18 +387,18 @@ static hipError_t enqueue_sweeps(hbf_ctx* c, void* zout, int R, bool adjoint, hi
   const bool v128 = c->dtype == HBF_C128;
   hipError_t e;
   if (!adjoint) {
-    e = run_launches(c, c->S.fwd, false, c->d_t, c->d_u, R, v128, -are, -aim, s);
-    if (e == hipSuccess && !paper) e = run_launches(c, c->S.diag, false, c->d_t, c->d_u, R, v128, 1.0, 0.0, s);
+    e = run_launches(c, c->S.fwd, false, c->d_t, c->d_u, R, v128, -are, -aim, s, true);
+    if (e == hipSuccess && !paper) e = run_launches(c, c->S.diag, false, c->d_t, c->d_u, R, v128, 1.0, 0.0, s, true);
     if (e == hipSuccess) {
       void* mid = paper ? c->d_t : c->d_u;
-      e = run_launches(c, c->S.bwd, false, zout, mid, R, v128, -1.0, 0.0, s);
+      e = run_launches(c, c->S.bwd, false, zout, mid, R, v128, -1.0, 0.0, s, true);
     }
   } else {
-    e = run_launches(c, c->S.adj_fwd, true, c->d_u, c->d_t, R, v128, -1.0, 0.0, s);
-    if (e == hipSuccess && !paper) e = run_launches(c, c->S.diag, true, c->d_u, c->d_t, R, v128, 1.0, 0.0, s);
+    e = run_launches(c, c->S.adj_fwd, true, c->d_u, c->d_t, R, v128, -1.0, 0.0, s, true);
+    if (e == hipSuccess && !paper) e = run_launches(c, c->S.diag, true, c->d_u, c->d_t, R, v128, 1.0, 0.0, s, true);
     if (e == hipSuccess) {
       void* mid = paper ? c->d_t : c->d_u;
-      e = run_launches(c, c->S.adj_bwd, true, mid, zout, R, v128, -are, aim, s);
+      e = run_launches(c, c->S.adj_bwd, true, mid, zout, R, v128, -are, aim, s, true);
     }
   }
   return e;
@@ -731,6 +733,13 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
   }
   if (k == "wave_units") { c->wave_units = value != 0; free_graphs(c); return HBF_OK; }
   if (k == "lane_split") { c->lane_split = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "sweep_rc1") { c->sweep_rc1 = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "sweep_pipe_max_r") {
+    if (value < 0 || value > 1024) return fail(HBF_EINVAL, "hbf_tune: sweep_pipe_max_r out of range");
+    c->sweep_pipe_max_r = static_cast<int>(value);
+    free_graphs(c);
+    return HBF_OK;
+  }
   if (k == "use_graphs") { c->use_graphs = value != 0; free_graphs(c); return HBF_OK; }
   if (k == "r1_max_blocks") {
     if (value < 1 || value > (1 << 20)) return fail(HBF_EINVAL, "hbf_tune: r1_max_blocks out of range");

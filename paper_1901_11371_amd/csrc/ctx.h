@@ -25,6 +25,8 @@ struct hbf_ctx {
   bool r1_kernel = false;      // register-streaming kernel for one-RHS launches (LDS atomics)
   bool prog_pipe = true;       // pipelined wave teams in the sweep programs
   bool lane_split = true;      // pipelined kernels: several lanes share one output of a small unit
+  bool sweep_rc1 = false;      // sweep stage launches above pipe_max_r: pipelined kernel, one RHS per chunk
+  int sweep_pipe_max_r = 4;    // pipe_max_r for the sweeps' stage launches
   int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
   int r1_max_blocks = 2048;    // persistent grid size of that kernel
 
@@ -63,9 +65,11 @@ struct hbf_ctx {
 namespace hbf {
 
 // Run a schedule on the device.  vec_c128: vectors are complex128 (with
-// complex64 factors this selects FP64 accumulation).
+// complex64 factors this selects FP64 accumulation).  sweep: the launches
+// belong to the preconditioner sweeps (their stage launches may run one RHS
+// per chunk in the pipelined kernel whatever the RHS count).
 hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
-                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s);
+                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep = false);
 
 hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s);
 hbf_status precond_internal(hbf_ctx* c, const void* rin, void* zout, int R, bool adjoint, hipStream_t s);

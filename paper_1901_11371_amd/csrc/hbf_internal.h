@@ -61,8 +61,8 @@ static_assert(sizeof(Unit) == 64, "Unit must be 64 bytes");
 
 // Program step table entries: first unit, end unit, flags (1 accumulate,
 // 2 forward mode, 4 all units are dense 8-row slabs with one input and one
-// output segment), first 16-entry granule of the step's matrices and the
-// number of granules they span.
+// output segment, 8 those slabs widen with the unit index), first 16-entry
+// granule of the step's matrices and the number of granules they span.
 constexpr int kStepInts = 5;
 
 // A launch of the stage kernel: a range of groups; a group is a list of units

@@ -70,7 +70,9 @@ struct SweepGen {
       }
       steps.push_back(u0);
       steps.push_back(u1);
-      steps.push_back(acc | (force_fwd << 1) | (slab ? 4 : 0));
+      // flag 8: the slab widths grow with the unit index (claim them from the end)
+      const bool rev = slab && P.units[u1 - 1].in_len[0] > P.units[u0].in_len[0];
+      steps.push_back(acc | (force_fwd << 1) | (slab ? 4 : 0) | (rev ? 8 : 0));
       steps.push_back(static_cast<int32_t>(m0 / 16));
       steps.push_back(static_cast<int32_t>((m1 + 15) / 16 - m0 / 16));
       prog->count += 1;

@@ -524,7 +524,7 @@ __device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, in
 // not depend on the sweep), its sources only after.
 template <class F, class V, class A, bool ADJ, bool NR1>
 __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave, int lane,
-                         unsigned char* lds, int32_t* s_steps, Unit* ring, int R, int r0, int nr) {
+                         unsigned char* lds, int32_t* s_steps, Unit* ring, int* s_ctr, int R, int r0, int nr) {
   constexpr int kCompute = prog_waves<F>() - 1;  // waves that take units; the last one prefetches
   const int tid = threadIdx.x;
   int w0 = s0;  // first step of the staged window
@@ -546,6 +546,10 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
       __syncthreads();
     }
   };
+  // slab steps (one RHS) run through slab_unit: the compute waves claim their
+  // units, widest first, from a counter in LDS that is cleared (behind one
+  // extra barrier) at the start of the step; they take no lookahead item
+  auto is_slab = [&](int st) { return NR1 && ((st_fl(st) >> 2) & 1); };
   load_window(s0);
   __syncthreads();
   {  // ring slots of the first two steps
@@ -567,6 +571,7 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
     int pst = s0 + 1, pdone = 0;  // cursor: step and lines of it already touched
     for (int st = s0; st < s1; ++st) {
       maybe_reload(st);
+      if (is_slab(st)) __syncthreads();
       u32x4 rv[4];
       int rcount = 0;
       if (st + 2 < s1) {
@@ -638,13 +643,20 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
   cx<A> acc[kOpt];
 #pragma unroll
   for (int j = 0; j < kOpt; ++j) acc[j] = cx<A>{0, 0};
-  // slab steps (one RHS) run through slab_unit and take no lookahead item
-  auto is_slab = [&](int st) { return NR1 && ((st_fl(st) >> 2) & 1); };
   for (int st = s0; st < s1; ++st) {
     maybe_reload(st);
     const int u0 = st_u0(st), u1 = st_u1(st), flags = st_fl(st);
     if (is_slab(st)) {
-      for (int q = u0 + wave; q < u1; q += kCompute) slab_unit<F, V, A>(a, desc_at(q, st), lane, R, r0);
+      if (tid == 0) *s_ctr = 0;
+      __syncthreads();
+      const bool rev = (flags >> 3) & 1;
+      for (;;) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(s_ctr, 1);
+        idx = uni(idx);
+        if (idx >= u1 - u0) break;
+        slab_unit<F, V, A>(a, desc_at(rev ? u1 - 1 - idx : u0 + idx, st), lane, R, r0);
+      }
     } else if (!have && u0 + wave < u1) {
       cq = u0 + wave;
       cc = 0;
@@ -741,8 +753,9 @@ __global__ void __launch_bounds__(64 * prog_waves<F>()) k_program_pipe(StageArgs
   const int nr = NR1 ? 1 : min(a.rc, a.R - r0);
   Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(prog_waves<F>()) * team_lds);
   int32_t* s_steps = reinterpret_cast<int32_t*>(ring + 3 * kDescMax);
+  int* s_ctr = reinterpret_cast<int*>(s_steps + kStepInts * kStepWin);
   prog_run<F, V, A, ADJ, NR1>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
-                         ring, a.R, r0, nr);
+                              ring, s_ctr, a.R, r0, nr);
 }
 
 }  // namespace
@@ -778,7 +791,8 @@ static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int
   const int lds1 = pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
   const dim3 grid(static_cast<unsigned>(a.nchunks));
   const size_t lds =
-      static_cast<size_t>(lds1) * prog_waves<F>() + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin;
+      static_cast<size_t>(lds1) * prog_waves<F>() + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin +
+      16;
   const dim3 block(64 * prog_waves<F>());
   const bool nr1 = a.rc == 1;
   if (adjoint && nr1)

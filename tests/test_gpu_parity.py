@@ -124,6 +124,9 @@ TUNINGS = [
     {"pipe_max_r": 0, "wave_units": 1},
     {"pipe_max_r": 0, "wave_units": 0},
     {"use_graphs": 0, "prog_levels": 4},
+    {"sweep_rc1": 1},
+    {"pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 1},
+    {"pipe_max_r": 8, "sweep_pipe_max_r": 8},
 ]
 
 
