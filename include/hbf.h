@@ -183,6 +183,8 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *                   (default 4),
  *   "sweep_rc1"     1 = the sweeps' stage launches with nrhs > sweep_pipe_max_r
  *                   use the pipelined kernel with one RHS per workgroup chunk,
+ *   "prog_lds"      1 = sweep programs whose vectors fit keep them in LDS
+ *                   (default 1),
  *   "use_graphs"    1 = replay the preconditioner sweeps from HIP graphs.
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);

@@ -57,6 +57,7 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_gofs);
   dfree(c->d_gunits);
   dfree(c->d_steps);
+  dfree(c->d_punits);
   dfree(c->d_arena);
   dfree(c->d_vin);
   dfree(c->d_vout);
@@ -227,6 +228,28 @@ hbf_status fail(hbf_status st, const std::string& msg) {
 
 namespace hbf {
 
+// Build the sweep schedules for the context's settings and upload their step
+// tables and unit copies (throws on allocation or copy failure).
+void rebuild_sweeps(hbf_ctx* c, int prog_levels) {
+  // LDS-resident programs exist only for the pipelined program kernel
+  const int lds_rows = (c->prog_lds && c->prog_pipe)
+                           ? prog_lds_rows_budget(static_cast<int>(c->elt), static_cast<int>(c->elt))
+                           : 0;
+  build_sweeps(c->P, c->S, prog_levels, lds_rows);
+  dfree(c->d_steps);
+  c->d_steps = nullptr;
+  dfree(c->d_punits);
+  c->d_punits = nullptr;
+  dmalloc(&c->d_steps, std::max<size_t>(c->S.steps.size(), 1) * sizeof(int32_t), "steps");
+  if (!c->S.steps.empty())
+    hip_check(hipMemcpy(c->d_steps, c->S.steps.data(), c->S.steps.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+              "steps");
+  dmalloc(&c->d_punits, std::max<size_t>(c->S.punits.size(), 1) * sizeof(Unit), "program units");
+  if (!c->S.punits.empty())
+    hip_check(hipMemcpy(c->d_punits, c->S.punits.data(), c->S.punits.size() * sizeof(Unit), hipMemcpyHostToDevice),
+              "program units");
+}
+
 hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
                         bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep) {
   const size_t szA = (vec_c128 || c->dtype == HBF_C128) ? 16 : 8;
@@ -236,7 +259,11 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     if (l.prog) {
       // one workgroup per RHS chunk; each wave is a pipelined team
       StageArgs a;
-      a.units = c->d_units;
+      const bool lv = l.lv_rows > 0;
+      a.units = lv ? c->d_punits : c->d_units;
+      a.lv_rows = lv ? l.lv_rows : 0;
+      a.prow0 = l.prow0;
+      a.prows = l.prows;
       a.gofs = c->d_gofs;
       a.gunits = c->d_gunits;
       a.fac = c->d_fac;
@@ -501,7 +528,6 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
         }
       }
     }
-    build_sweeps(c->P, c->S);
     Plan& P = c->P;
     c->n = P.n;
     const int64_t N = P.n;
@@ -539,10 +565,7 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     hip_check(hipMemcpy(c->d_gunits, P.group_units.data(), P.group_units.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice),
               "groups");
-    dmalloc(&c->d_steps, std::max<size_t>(c->S.steps.size(), 1) * sizeof(int32_t), "steps");
-    if (!c->S.steps.empty())
-      hip_check(hipMemcpy(c->d_steps, c->S.steps.data(), c->S.steps.size() * sizeof(int32_t), hipMemcpyHostToDevice),
-                "steps");
+    rebuild_sweeps(c.get(), c->S.prog_levels);
     const size_t R = static_cast<size_t>(c->max_nrhs);
     const size_t vbytes = static_cast<size_t>(N) * R * 16;
     dmalloc(&c->d_arena, static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16, "arena");
@@ -575,7 +598,8 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       c->stats.apply_bytes_precond =
           c->prec == HBF_PREC_NONE
               ? vec
-              : schedule_bytes(P, c->S.fwd, &c->S.steps, c->elt) + schedule_bytes(P, c->S.bwd, &c->S.steps, c->elt) +
+              : schedule_bytes(P, c->S.fwd, &c->S.steps, c->elt, &c->S.punits) +
+                    schedule_bytes(P, c->S.bwd, &c->S.steps, c->elt, &c->S.punits) +
                     (c->prec == HBF_PREC_BLOCK_LU ? schedule_bytes(P, c->S.diag, nullptr, c->elt) : 0) + vec;
     }
     std::vector<cplx>().swap(P.fac);
@@ -709,22 +733,36 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     if (value < 0 || value > 12) return fail(HBF_EINVAL, "hbf_tune: prog_levels out of range");
     (void)hipDeviceSynchronize();
     free_graphs(c);
-    build_sweeps(c->P, c->S, static_cast<int>(value));
-    dfree(c->d_steps);
-    c->d_steps = nullptr;
     try {
-      dmalloc(&c->d_steps, std::max<size_t>(c->S.steps.size(), 1) * sizeof(int32_t), "steps");
-    } catch (...) {
-      return fail(HBF_ENOMEM, "hbf_tune: out of device memory");
+      rebuild_sweeps(c, static_cast<int>(value));
+    } catch (const std::exception& e) {
+      return fail(HBF_ENOMEM, std::string("hbf_tune: ") + e.what());
     }
-    if (!c->S.steps.empty() &&
-        hipMemcpy(c->d_steps, c->S.steps.data(), c->S.steps.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-            hipSuccess)
-      return fail(HBF_EHIP, "hbf_tune: upload");
+    return HBF_OK;
+  }
+  if (k == "prog_lds") {
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    c->prog_lds = value != 0;
+    try {
+      rebuild_sweeps(c, c->S.prog_levels);
+    } catch (const std::exception& e) {
+      return fail(HBF_ENOMEM, std::string("hbf_tune: ") + e.what());
+    }
     return HBF_OK;
   }
   if (k == "r1_kernel") { c->r1_kernel = value != 0; free_graphs(c); return HBF_OK; }
-  if (k == "prog_pipe") { c->prog_pipe = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "prog_pipe") {
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    c->prog_pipe = value != 0;
+    try {
+      rebuild_sweeps(c, c->S.prog_levels);
+    } catch (const std::exception& e) {
+      return fail(HBF_ENOMEM, std::string("hbf_tune: ") + e.what());
+    }
+    return HBF_OK;
+  }
   if (k == "pipe_max_r") {
     if (value < 0 || value > 1024) return fail(HBF_EINVAL, "hbf_tune: pipe_max_r out of range");
     c->pipe_max_r = static_cast<int>(value);

@@ -27,6 +27,7 @@ struct hbf_ctx {
   bool lane_split = true;      // pipelined kernels: several lanes share one output of a small unit
   bool sweep_rc1 = false;      // sweep stage launches above pipe_max_r: pipelined kernel, one RHS per chunk
   int sweep_pipe_max_r = 4;    // pipe_max_r for the sweeps' stage launches
+  bool prog_lds = true;        // sweep programs keep their vectors in LDS where they fit
   int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
   int r1_max_blocks = 2048;    // persistent grid size of that kernel
 
@@ -37,6 +38,7 @@ struct hbf_ctx {
   int32_t* d_gofs = nullptr;
   int32_t* d_gunits = nullptr;
   int32_t* d_steps = nullptr;  // program steps of the sweeps
+  hbf::Unit* d_punits = nullptr;  // unit copies of the programs with LDS-resident vectors
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
   void* d_vin = nullptr;       // internal-layout vectors, N x max_nrhs x 16 bytes each
   void* d_vout = nullptr;

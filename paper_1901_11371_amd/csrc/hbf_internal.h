@@ -80,7 +80,16 @@ struct Launch {
   int32_t prog = 0;    // 1: a sequential program over steps [first, first+count) of the step table
   int32_t force_fwd = 0;  // 1: apply the units in forward mode even in an adjoint schedule
   int32_t single = 1;     // 1: every group is one unit (no accumulation across units)
+  // program kept in LDS (lv_rows > 0): its steps index the rewritten unit
+  // copies of Sweeps::punits, whose vector segments are LDS rows: the
+  // program's rows [prow0, prow0 + prows) of X at [0, prows), of Y at
+  // [prows, 2 prows), and every skeleton segment it touches after them
+  int32_t lv_rows = 0;
+  int32_t prow0 = 0, prows = 0;
 };
+enum : uint8_t { BUF_LDS = 3 };  // a segment of a program's LDS-resident vectors
+
+
 
 // Per-butterfly-block bookkeeping.
 struct BlockInfo {

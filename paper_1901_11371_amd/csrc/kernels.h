@@ -32,6 +32,8 @@ struct StageArgs {
   int32_t src_cap;        // LDS source capacity (rows x rc entries)
   int32_t split = 1;      // 1: up to 32 lanes may share one output of a small unit (pipelined kernels)
   int32_t single = 0;     // 1: every group is one unit (lanes may then share an output)
+  int32_t lv_rows = 0;    // program with LDS-resident vectors: LDS rows (0: vectors in memory)
+  int32_t prow0 = 0, prows = 0;  // ... and its rows of the X and Y vectors
 };
 
 constexpr int kStageThreads = 256;
@@ -48,6 +50,10 @@ hipError_t launch_stage_c64_hi(const StageArgs& a, int ngroups, bool adjoint, si
 // Software-pipelined wave teams (stage_pipe.hip): stage launches over
 // ngroups groups x nchunks RHS chunks, and sweep programs.
 int pipe_team_lds(int elt_acc, int elt_fac);
+int prog_team_lds_lv(int elt_fac);
+// Largest vector footprint (rows of elt_vec bytes) a sweep program can keep in
+// LDS next to its staging areas.
+int prog_lds_rows_budget(int elt_fac, int elt_vec);
 hipError_t launch_pipe_c64(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s);
 hipError_t launch_pipe_c128(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s);
 hipError_t launch_pipe_c64_hi(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks,

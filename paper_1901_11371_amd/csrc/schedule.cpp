@@ -12,6 +12,7 @@
 #include <thread>
 
 #include "hbf_internal.h"
+#include "kernels.h"
 #include "schedule.h"
 
 namespace hbf {
@@ -41,6 +42,133 @@ struct SweepGen {
   std::vector<Launch>& out;
   std::vector<int32_t>& steps;
   int prog_levels;
+  std::vector<Unit>* punits = nullptr;
+  int lds_rows = 0;
+
+  // Keep the program over rows [r0, r0 + nrows) in LDS if its vectors fit:
+  // copy its units with every segment remapped to LDS rows (X rows at
+  // [0, nrows), Y rows at [nrows, 2 nrows), each skeleton segment packed
+  // after them) and point its steps at the copies.
+  void make_lds(Launch& l, int64_t r0, int64_t nrows) const {
+    if (!punits || lds_rows <= 0) return;
+    std::vector<std::pair<int32_t, int32_t>> segs;  // arena (offset, length)
+    for (int st = l.first; st < l.first + l.count; ++st) {
+      for (int32_t q = steps[kStepInts * st]; q < steps[kStepInts * st + 1]; ++q) {
+        const Unit& u = P.units[q];
+        for (int side = 0; side < 2; ++side) {
+          const uint8_t buf = side ? u.out_buf : u.in_buf;
+          const int32_t* off = side ? u.out_off : u.in_off;
+          const int16_t* len = side ? u.out_len : u.in_len;
+          for (int sgi = 0; sgi < 2; ++sgi) {
+            if (len[sgi] <= 0) continue;
+            if (buf == BUF_ARENA) segs.push_back({off[sgi], len[sgi]});
+            else if (off[sgi] < r0 || off[sgi] + len[sgi] > r0 + nrows) return;
+          }
+        }
+      }
+    }
+    std::sort(segs.begin(), segs.end());
+    segs.erase(std::unique(segs.begin(), segs.end()), segs.end());
+    for (size_t i = 1; i < segs.size(); ++i)
+      if (segs[i].first < segs[i - 1].first + segs[i - 1].second) return;  // overlapping segments
+    // A skeleton segment's value lives from the step that writes it to the
+    // last step that reads it (steps are separated by workgroup barriers), so
+    // segments whose lives do not overlap share LDS rows.  refs: every arena
+    // reference in step order (segment, instance); an instance starts at a
+    // write.  A read of a segment no earlier step of the program wrote keeps
+    // the program in HBM.
+    struct Ref { size_t seg; int32_t inst; };
+    std::vector<Ref> refs;
+    std::vector<int32_t> inst_seg, inst_write, inst_last;  // per instance
+    auto seg_index = [&](int32_t o, int16_t n) {
+      return static_cast<size_t>(
+          std::lower_bound(segs.begin(), segs.end(), std::pair<int32_t, int32_t>(o, static_cast<int32_t>(n))) -
+          segs.begin());
+    };
+    {
+      std::vector<int32_t> live(segs.size(), -1);
+      for (int st = l.first; st < l.first + l.count; ++st) {
+        // adjoint steps read the units' output segments and write their inputs
+        const int read_side = (adjoint && !(steps[kStepInts * st + 2] & 2)) ? 1 : 0;
+        for (int32_t q = steps[kStepInts * st]; q < steps[kStepInts * st + 1]; ++q) {
+          const Unit& u = P.units[q];
+          for (int side = 0; side < 2; ++side) {
+            if ((side ? u.out_buf : u.in_buf) != BUF_ARENA) continue;
+            const int32_t* off = side ? u.out_off : u.in_off;
+            const int16_t* len = side ? u.out_len : u.in_len;
+            for (int sgi = 0; sgi < 2; ++sgi) {
+              if (len[sgi] <= 0) continue;
+              const size_t i = seg_index(off[sgi], len[sgi]);
+              if (side == read_side) {
+                if (live[i] < 0 || inst_write[live[i]] >= st) return;
+                inst_last[live[i]] = st;
+              } else if (live[i] < 0 || inst_write[live[i]] != st) {
+                live[i] = static_cast<int32_t>(inst_seg.size());
+                inst_seg.push_back(static_cast<int32_t>(i));
+                inst_write.push_back(st);
+                inst_last.push_back(st);
+              }
+              refs.push_back({i, live[i]});
+            }
+          }
+        }
+      }
+    }
+    // first-fit placement from row 2 nrows on, in order of the writing step
+    std::vector<int32_t> inst_row(inst_seg.size(), -1);
+    int64_t total = 2 * nrows;
+    {
+      std::vector<std::pair<int64_t, int32_t>> used;  // (row, instance), sorted by row
+      size_t k = 0;
+      for (int st = l.first; st < l.first + l.count && k < inst_seg.size(); ++st) {
+        used.erase(std::remove_if(used.begin(), used.end(),
+                                  [&](const std::pair<int64_t, int32_t>& e) { return inst_last[e.second] < st; }),
+                   used.end());
+        for (; k < inst_seg.size() && inst_write[k] == st; ++k) {
+          const int64_t need = segs[inst_seg[k]].second;
+          int64_t row = 2 * nrows;
+          size_t pos = 0;
+          for (; pos < used.size(); ++pos) {
+            if (used[pos].first - row >= need) break;
+            row = std::max(row, used[pos].first + segs[inst_seg[used[pos].second]].second);
+          }
+          used.insert(used.begin() + static_cast<std::ptrdiff_t>(pos), {row, static_cast<int32_t>(k)});
+          inst_row[k] = static_cast<int32_t>(row);
+          total = std::max(total, row + need);
+        }
+      }
+    }
+    std::vector<int32_t> slots(refs.size());
+    for (size_t k = 0; k < refs.size(); ++k) slots[k] = inst_row[refs[k].inst];
+    if (total > lds_rows) return;
+    size_t next_slot = 0;
+    auto remap = [&](uint8_t& buf, int32_t* off, const int16_t* len) {
+      for (int sgi = 0; sgi < 2; ++sgi) {
+        if (len[sgi] <= 0) continue;
+        if (buf == BUF_ARENA) {
+          off[sgi] = slots[next_slot++];
+        } else {
+          off[sgi] = static_cast<int32_t>(off[sgi] - r0 + (buf == BUF_Y ? nrows : 0));
+        }
+      }
+      buf = BUF_LDS;
+    };
+    for (int st = l.first; st < l.first + l.count; ++st) {
+      const int32_t u0 = steps[kStepInts * st], u1 = steps[kStepInts * st + 1];
+      const int32_t c0 = static_cast<int32_t>(punits->size());
+      for (int32_t q = u0; q < u1; ++q) {
+        Unit u = P.units[q];
+        remap(u.in_buf, u.in_off, u.in_len);
+        remap(u.out_buf, u.out_off, u.out_len);
+        punits->push_back(u);
+      }
+      steps[kStepInts * st] = c0;
+      steps[kStepInts * st + 1] = c0 + (u1 - u0);
+    }
+    l.lv_rows = static_cast<int32_t>(total);
+    l.prow0 = static_cast<int32_t>(r0);
+    l.prows = static_cast<int32_t>(nrows);
+  }
 
   void bound(Launch& l, int32_t u0, int32_t u1) const {
     for (int32_t u = u0; u < u1; ++u) {
@@ -102,6 +230,8 @@ struct SweepGen {
       l.kind = 2;
       l.prog = 1;
       rec(dd, idx, &l);
+      const int64_t rows = static_cast<int64_t>(P.n0) << (P.V - dd);
+      make_lds(l, idx * rows, rows);
       out.push_back(l);
       return;
     }
@@ -132,7 +262,7 @@ struct SweepGen {
 
 }  // namespace
 
-void build_sweeps(const Plan& P, Sweeps& S, int prog_levels) {
+void build_sweeps(const Plan& P, Sweeps& S, int prog_levels, int lds_rows) {
   std::vector<int> level_base(P.V + 1, 0);
   {
     int cur = 0;
@@ -146,17 +276,26 @@ void build_sweeps(const Plan& P, Sweeps& S, int prog_levels) {
   S.adj_fwd.clear();
   S.adj_bwd.clear();
   S.steps.clear();
+  S.punits.clear();
   S.prog_levels = prog_levels;
   if (P.sl_fwd.empty()) return;
   // P^{-1}: lower sweep with the L~ super-leaf inverses, upper with the U~ ones.
   // P^{-H}: lower sweep with (U~ inverse)^H, upper with (L~ inverse)^H.
   SweepGen g1{P, level_base, true, false, P.sl_fwd, S.fwd, S.steps, prog_levels};
+  g1.punits = &S.punits;
+  g1.lds_rows = lds_rows;
   g1.rec(0, 0, nullptr);
   SweepGen g2{P, level_base, false, false, P.sl_bwd, S.bwd, S.steps, prog_levels};
+  g2.punits = &S.punits;
+  g2.lds_rows = lds_rows;
   g2.rec(0, 0, nullptr);
   SweepGen g3{P, level_base, true, true, P.sl_adj_fwd, S.adj_fwd, S.steps, prog_levels};
+  g3.punits = &S.punits;
+  g3.lds_rows = lds_rows;
   g3.rec(0, 0, nullptr);
   SweepGen g4{P, level_base, false, true, P.sl_adj_bwd, S.adj_bwd, S.steps, prog_levels};
+  g4.punits = &S.punits;
+  g4.lds_rows = lds_rows;
   g4.rec(0, 0, nullptr);
   // the block reading's middle vector s = D t uses the diagonal leaf units
   const int64_t nl = P.n / P.n0;
@@ -274,15 +413,17 @@ void unit_eval(const Plan& P, const Unit& u, bool adj, const std::vector<cplx>& 
 }  // namespace
 
 int64_t schedule_bytes(const Plan& P, const std::vector<Launch>& launches, const std::vector<int32_t>* steps,
-                       int elt) {
+                       int elt, const std::vector<Unit>* punits) {
   int64_t total = 0;
+  const std::vector<Unit>* table = &P.units;
   auto add = [&](int32_t uid) {
-    const Unit& u = P.units[uid];
+    const Unit& u = (*table)[uid];
     total += static_cast<int64_t>(u.mat_len) * elt + static_cast<int64_t>(sizeof(Unit));
     if (u.type == UNIT_GATHER) total += 2 * (u.in_len[0] + u.in_len[1]);
     if (u.type == UNIT_SCATTER) total += 2 * (u.out_len[0] + u.out_len[1]);
   };
   for (const Launch& L : launches) {
+    table = (L.prog && L.lv_rows > 0 && punits) ? punits : &P.units;
     if (L.prog) {
       for (int st = L.first; st < L.first + L.count; ++st)
         for (int32_t q = (*steps)[kStepInts * st]; q < (*steps)[kStepInts * st + 1]; ++q) add(q);
@@ -296,30 +437,14 @@ int64_t schedule_bytes(const Plan& P, const std::vector<Launch>& launches, const
   return total;
 }
 
-void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cplx* X, cplx* Y,
-               cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps) {
-  auto bufp = [&](uint8_t id) -> cplx* { return id == BUF_X ? X : id == BUF_Y ? Y : arena; };
-  std::vector<cplx> src, dst;
-  std::vector<Launch> expanded;
-  for (const Launch& L0 : launches) {
-    if (L0.prog) {
-      // a program is its steps, in order
-      for (int st = L0.first; st < L0.first + L0.count; ++st) {
-        Launch l = L0;
-        l.prog = 0;
-        l.direct = 1;
-        l.first = (*steps)[kStepInts * st];
-        l.count = (*steps)[kStepInts * st + 1] - (*steps)[kStepInts * st];
-        l.out_leaf = (*steps)[kStepInts * st + 2] & 1;
-        l.force_fwd = ((*steps)[kStepInts * st + 2] >> 1) & 1;
-        expanded.push_back(l);
-      }
-    } else {
-      expanded.push_back(L0);
-    }
-  }
-  const bool adj_all = adj;
-  for (const Launch& L : expanded) {
+void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj_all, cplx* X, cplx* Y,
+               cplx* arena, int R, cplx alpha, const std::vector<int32_t>* steps, const std::vector<Unit>* punits) {
+  std::vector<cplx> src, dst, lds;
+  // one ordered launch over `units`; BUF_LDS names the emulated LDS rows
+  auto run = [&](const Launch& L, const Unit* units) {
+    auto bufp = [&](uint8_t id) -> cplx* {
+      return id == BUF_X ? X : id == BUF_Y ? Y : id == BUF_LDS ? lds.data() : arena;
+    };
     const bool adj = adj_all && !L.force_fwd;
     for (int g = L.first; g < L.first + L.count; ++g) {
       std::vector<int32_t> us;
@@ -329,7 +454,7 @@ void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cpl
         for (int32_t q = P.group_off[g]; q < P.group_off[g + 1]; ++q) us.push_back(P.group_units[q]);
       }
       // destination segments are those of the first unit (shared by the group)
-      const Unit& u0 = P.units[us[0]];
+      const Unit& u0 = units[us[0]];
       const uint8_t dbuf = adj ? u0.in_buf : u0.out_buf;
       const int32_t* doff = adj ? u0.in_off : u0.out_off;
       const int16_t* dlen = adj ? u0.in_len : u0.out_len;
@@ -337,7 +462,7 @@ void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cpl
       for (int r = 0; r < R; ++r) {
         dst.assign(nd, cplx(0.0));
         for (int32_t uid : us) {
-          const Unit& u = P.units[uid];
+          const Unit& u = units[uid];
           const uint8_t sbuf = adj ? u.out_buf : u.in_buf;
           const int32_t* soff = adj ? u.out_off : u.in_off;
           const int16_t* slen = adj ? u.out_len : u.in_len;
@@ -357,6 +482,36 @@ void exec_host(const Plan& P, const std::vector<Launch>& launches, bool adj, cpl
           }
         }
       }
+    }
+  };
+  for (const Launch& L0 : launches) {
+    if (!L0.prog) {
+      run(L0, P.units.data());
+      continue;
+    }
+    // a program is its steps, in order; with LDS-resident vectors its rows
+    // of X and Y are copied in before the first step and out after the last
+    const bool lv = L0.lv_rows > 0;
+    if (lv && !punits) throw std::logic_error("exec_host: LDS-resident program without its unit copies");
+    const int64_t r0 = L0.prow0, nr = L0.prows;
+    if (lv) {
+      lds.assign(static_cast<size_t>(L0.lv_rows) * R, cplx(std::nan(""), 0.0));
+      std::copy(X + r0 * R, X + (r0 + nr) * R, lds.begin());
+      std::copy(Y + r0 * R, Y + (r0 + nr) * R, lds.begin() + nr * R);
+    }
+    for (int st = L0.first; st < L0.first + L0.count; ++st) {
+      Launch l = L0;
+      l.prog = 0;
+      l.direct = 1;
+      l.first = (*steps)[kStepInts * st];
+      l.count = (*steps)[kStepInts * st + 1] - (*steps)[kStepInts * st];
+      l.out_leaf = (*steps)[kStepInts * st + 2] & 1;
+      l.force_fwd = ((*steps)[kStepInts * st + 2] >> 1) & 1;
+      run(l, lv ? punits->data() : P.units.data());
+    }
+    if (lv) {
+      std::copy(lds.begin(), lds.begin() + nr * R, X + r0 * R);
+      std::copy(lds.begin() + nr * R, lds.begin() + 2 * nr * R, Y + r0 * R);
     }
   }
 }
@@ -515,7 +670,10 @@ hbf_status hbf_plan_build(const hbf_curve* curve, double kappa, int32_t leaf, do
     build_plan(p->P, curve, kappa, leaf, tol, opts);
     p->prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
     host_leaf_factor(p->P, p->prec);
-    build_sweeps(p->P, p->S);
+    // the device's default sweep schedule: programs over subtrees of 2^5
+    // leaves, vectors LDS-resident where they fit the storage dtype's budget
+    const int elt = (opts && opts->dtype == HBF_C128) ? 16 : 8;
+    build_sweeps(p->P, p->S, 5, prog_lds_rows_budget(elt, elt));
     *out = p.release();
     return HBF_OK;
   } catch (const std::invalid_argument& e) {
@@ -562,15 +720,15 @@ hbf_status hbf_plan_precond(const hbf_plan* plan, const double* rin, double* zou
     const bool paper = plan->prec == HBF_PREC_PAPER_TRI;
     const cplx a = paper ? P.scale : cplx(1.0);
     if (!adjoint) {
-      exec_host(P, S.fwd, false, t.data(), u.data(), arena.data(), nrhs, -a, &S.steps);
+      exec_host(P, S.fwd, false, t.data(), u.data(), arena.data(), nrhs, -a, &S.steps, &S.punits);
       if (!paper) exec_host(P, S.diag, false, t.data(), u.data(), arena.data(), nrhs, 0.0);  // u = D t
       cplx* mid = paper ? t.data() : u.data();
-      exec_host(P, S.bwd, false, z.data(), mid, arena.data(), nrhs, -1.0, &S.steps);
+      exec_host(P, S.bwd, false, z.data(), mid, arena.data(), nrhs, -1.0, &S.steps, &S.punits);
     } else {
-      exec_host(P, S.adj_fwd, true, u.data(), t.data(), arena.data(), nrhs, -1.0, &S.steps);
+      exec_host(P, S.adj_fwd, true, u.data(), t.data(), arena.data(), nrhs, -1.0, &S.steps, &S.punits);
       if (!paper) exec_host(P, S.diag, true, u.data(), t.data(), arena.data(), nrhs, 0.0);  // u = D^H t
       cplx* mid = paper ? t.data() : u.data();
-      exec_host(P, S.adj_bwd, true, mid, z.data(), arena.data(), nrhs, -std::conj(a), &S.steps);
+      exec_host(P, S.adj_bwd, true, mid, z.data(), arena.data(), nrhs, -std::conj(a), &S.steps, &S.punits);
     }
   }
   for (int r = 0; r < nrhs; ++r)

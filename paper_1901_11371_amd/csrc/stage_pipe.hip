@@ -171,21 +171,24 @@ __device__ __forceinline__ void issue(const StageArgs& a, const UDesc& d, int c,
   if (c == 0) issue_src<F, V, A, ADJ>(a, d, lane, R, r0, nr, s);
 }
 
-// Stage the slot's item in LDS (sources and permutations for a unit's first chunk).
-template <class F, class V, class A>
+// Stage the slot's item in LDS (sources and permutations for a unit's first
+// chunk; SRC = false: the sources are read in place from LDS-resident vectors).
+template <class F, class V, class A, bool SRC = true>
 __device__ __forceinline__ void commit(const UDesc& d, int c, int lane, int nr, const Slot<V>& slot, cx<A>* s_src,
                                        uint8_t* s_p, uint8_t* s_q, u32x4* s_m4) {
   if (c == 0) {
+    if constexpr (SRC) {
 #pragma unroll
-    for (int j = 0; j < kSrcPL; ++j) {
-      const int e = lane + 64 * j;
-      if (e < d.n_src * nr) s_src[e] = up<A>(slot.sv[j]);
+      for (int j = 0; j < kSrcPL; ++j) {
+        const int e = lane + 64 * j;
+        if (e < d.n_src * nr) s_src[e] = up<A>(slot.sv[j]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < kPermPL; ++j) {
       const int e = lane + 64 * j;
       if (e < 2 * d.plen) {
-        const int o = e / d.plen, p = e - o * d.plen;
+        const int o = e >= d.plen ? 1 : 0, p = e - o * d.plen;
         s_p[o * 256 + p] = slot.pv[j];
         s_q[o * 256 + slot.pv[j]] = static_cast<uint8_t>(p);
       }
@@ -210,8 +213,10 @@ __device__ __forceinline__ int lanes_per_output_log2(int nout, bool split) {
   return lp;
 }
 
-template <class F, class A, bool ADJ>
-__device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, int nr, const cx<A>* s_src,
+// srcf(t, rr): source entry t of RHS rr of the unit (staged in LDS, or read
+// in place from a program's LDS-resident vectors).
+template <class F, class A, bool ADJ, class SrcF>
+__device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, int nr, const SrcF& srcf,
                                              const uint8_t* s_p, const uint8_t* s_q, const cx<F>* s_mat,
                                              cx<A>* acc, bool split) {
   constexpr int kChunkE = kChunkW * 16 / static_cast<int>(sizeof(cx<F>));
@@ -232,7 +237,7 @@ __device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, in
     const int o = p / nr;
     const int rr = p - o * nr;
     cx<A> s = acc[j];
-    auto S = [&](int t) { return s_src[t * nr + rr]; };
+    auto S = [&](int t) -> cx<A> { return srcf(t, rr); };
     auto MAC = [&](int e, int t) {
       const cx<A> m = up<A>(s_mat[e - e0]);
       if (ADJ) cmac_conj(s, m, S(t));
@@ -336,12 +341,13 @@ __device__ __forceinline__ void compute_item(const UDesc& d, int c, int lane, in
   }
 }
 
-// Write a finished unit's (or group's) destination and clear the accumulators.
-template <class V, class A>
+// Write a finished unit's (or group's) destination and clear the accumulators
+// (LVD: the destination rows are rows of a program's LDS-resident vectors lvv).
+template <class V, class A, bool LVD = false>
 __device__ __forceinline__ void write_dst(const StageArgs& a, const UDesc& d, int acc_mode, double alpha_re,
                                           double alpha_im, int lane, int R, int r0, int nr, cx<A>* acc,
-                                          bool split) {
-  V* db = reinterpret_cast<V*>(bufp(a, d.d_buf));
+                                          bool split, V* lvv = nullptr) {
+  V* db = LVD ? lvv : reinterpret_cast<V*>(bufp(a, d.d_buf));
   const A are = static_cast<A>(alpha_re), aim = static_cast<A>(alpha_im);
   const int lp = lanes_per_output_log2(d.n_dst * nr, split);
   const int P = 1 << lp;
@@ -362,7 +368,7 @@ __device__ __forceinline__ void write_dst(const StageArgs& a, const UDesc& d, in
     const int o = p / nr;
     const int rr = p - o * nr;
     const int row = (o < d.d_len0) ? d.d_off0 + o : d.d_off1 + (o - d.d_len0);
-    V* dp = &db[static_cast<int64_t>(row) * R + r0 + rr];
+    V* dp = LVD ? &db[row] : &db[static_cast<int64_t>(row) * R + r0 + rr];
     cx<A> v = acc[j];
     if (acc_mode) {
       const cx<A> cu = up<A>(*dp);
@@ -438,7 +444,8 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
       if (nxt.c == 0) dn = read_desc<ADJ, F>(unit_of(nxt.q));
       issue<F, V, A, ADJ>(a, dn, nxt.c, lane, R, r0, nr, slot);
     }
-    compute_item<F, A, ADJ>(d, cur.c, lane, nr, s_src, s_p, s_q, s_mat, acc, (a.direct || a.single) && a.split);
+    const auto srcf = [&](int t, int rr) -> cx<A> { return s_src[t * nr + rr]; };
+    compute_item<F, A, ADJ>(d, cur.c, lane, nr, srcf, s_p, s_q, s_mat, acc, (a.direct || a.single) && a.split);
     if (group_end)
       write_dst<V, A>(a, d, a.acc, a.alpha_re, a.alpha_im, lane, R, r0, nr, acc, (a.direct || a.single) && a.split);
     wsync();
@@ -453,13 +460,13 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
 // registers with coalesced 16-byte loads (lane l, load k: word l + 64 k, so a
 // wave instruction reads one contiguous kilobyte), together with the matching
 // input entries; lanes holding the same rows reduce by shuffles.
-template <class F, class V, class A>
-__device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, int lane, int R, int r0) {
+template <class F, class V, class A, bool LV>
+__device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, int lane, int R, int r0, V* lvv) {
   constexpr int EP = 16 / static_cast<int>(sizeof(cx<F>));  // complex entries per 16-byte word
   constexpr int G = 8 / EP;                                  // words per column
   constexpr int B = 4;                                       // words in flight per lane
   const u32x4* gm = reinterpret_cast<const u32x4*>(reinterpret_cast<const cx<F>*>(a.fac) + d.mat);
-  const V* xb = reinterpret_cast<const V*>(bufp(a, d.s_buf));
+  const V* xb = LV ? lvv : reinterpret_cast<const V*>(bufp(a, d.s_buf));
   const int nw = d.n_src * G;
   cx<A> acc[EP];
 #pragma unroll
@@ -472,7 +479,7 @@ __device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, in
       const int wi = k0 + 64 * b + lane;
       if (wi < nw) {
         m[b] = __builtin_nontemporal_load(&gm[wi]);
-        xv[b] = xb[static_cast<int64_t>(d.s_off0 + wi / G) * R + r0];
+        xv[b] = LV ? xb[d.s_off0 + wi / G] : xb[static_cast<int64_t>(d.s_off0 + wi / G) * R + r0];
       }
     }
 #pragma unroll
@@ -500,12 +507,14 @@ __device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, in
     }
   }
   if (lane < G) {
-    V* db = reinterpret_cast<V*>(bufp(a, d.d_buf));
+    V* db = LV ? lvv : reinterpret_cast<V*>(bufp(a, d.d_buf));
     using VT = decltype(db->x);
 #pragma unroll
-    for (int q = 0; q < EP; ++q)
-      db[static_cast<int64_t>(d.d_off0 + EP * lane + q) * R + r0] =
+    for (int q = 0; q < EP; ++q) {
+      const int row = d.d_off0 + EP * lane + q;
+      db[LV ? static_cast<int64_t>(row) : static_cast<int64_t>(row) * R + r0] =
           V{static_cast<VT>(acc[q].x), static_cast<VT>(acc[q].y)};
+    }
   }
 }
 
@@ -522,9 +531,10 @@ __device__ __forceinline__ void slab_unit(const StageArgs& a, const UDesc& d, in
 // (also when it has nothing to do in the current one); the permutations and
 // matrix chunk of that item are requested before the step barrier (they do
 // not depend on the sweep), its sources only after.
-template <class F, class V, class A, bool ADJ, bool NR1>
+template <class F, class V, class A, bool ADJ, bool NR1, bool LV>
 __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s1, int wave, int lane,
-                         unsigned char* lds, int32_t* s_steps, Unit* ring, int* s_ctr, int R, int r0, int nr) {
+                         unsigned char* lds, int32_t* s_steps, Unit* ring, int* s_ctr, V* lvv, int R, int r0,
+                         int nr) {
   constexpr int kCompute = prog_waves<F>() - 1;  // waves that take units; the last one prefetches
   const int tid = threadIdx.x;
   int w0 = s0;  // first step of the staged window
@@ -551,6 +561,14 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
   // extra barrier) at the start of the step; they take no lookahead item
   auto is_slab = [&](int st) { return NR1 && ((st_fl(st) >> 2) & 1); };
   load_window(s0);
+  if constexpr (LV) {  // the program's rows of X and Y into LDS
+    const V* X = reinterpret_cast<const V*>(a.buf[BUF_X]);
+    const V* Y = reinterpret_cast<const V*>(a.buf[BUF_Y]);
+    for (int e = tid; e < a.prows; e += blockDim.x) {
+      lvv[e] = X[static_cast<int64_t>(a.prow0 + e) * R + r0];
+      lvv[a.prows + e] = Y[static_cast<int64_t>(a.prow0 + e) * R + r0];
+    }
+  }
   __syncthreads();
   {  // ring slots of the first two steps
     for (int st = s0; st < min(s1, s0 + 2); ++st) {
@@ -620,8 +638,9 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
   }
 
   // ---------------- compute waves ----------------
+  // (LV: no source staging; the wave's LDS starts with the permutations)
   cx<A>* s_src = reinterpret_cast<cx<A>*>(lds);
-  uint8_t* s_p = reinterpret_cast<uint8_t*>(s_src + 256);
+  uint8_t* s_p = LV ? reinterpret_cast<uint8_t*>(lds) : reinterpret_cast<uint8_t*>(s_src + 256);
   uint8_t* s_q = s_p + 512;
   u32x4* s_m4 = reinterpret_cast<u32x4*>(s_q + 512);
   const cx<F>* s_mat = reinterpret_cast<const cx<F>*>(s_m4);
@@ -655,7 +674,7 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
         if (lane == 0) idx = atomicAdd(s_ctr, 1);
         idx = uni(idx);
         if (idx >= u1 - u0) break;
-        slab_unit<F, V, A>(a, desc_at(rev ? u1 - 1 - idx : u0 + idx, st), lane, R, r0);
+        slab_unit<F, V, A, LV>(a, desc_at(rev ? u1 - 1 - idx : u0 + idx, st), lane, R, r0, lvv);
       }
     } else if (!have && u0 + wave < u1) {
       cq = u0 + wave;
@@ -667,9 +686,9 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
       src_ready = false;
     }
     while (have && cst == st) {
-      if (cc == 0 && !src_ready) issue_src<F, V, A, ADJ>(a, d, lane, R, r0, nr, slot);
+      if (!LV && cc == 0 && !src_ready) issue_src<F, V, A, ADJ>(a, d, lane, R, r0, nr, slot);
       const int nch = d.nwords > 0 ? (d.nwords + kChunkW - 1) / kChunkW : 1;
-      commit<F, V, A>(d, cc, lane, nr, slot, s_src, s_p, s_q, s_m4);
+      commit<F, V, A, !LV>(d, cc, lane, nr, slot, s_src, s_p, s_q, s_m4);
       wsync();
       // next item
       int nq = cq, nc = cc + 1, nst = st;
@@ -692,17 +711,26 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
       if (nhave) {
         if (nc == 0) dn = desc_at(nq, nst);
         issue_static<F, V, A, ADJ>(a, dn, nc, lane, slot);
-        if (nc == 0 && nst == st) {  // same step: its sources are final already
+        if (!LV && nc == 0 && nst == st) {  // same step: its sources are final already
           issue_src<F, V, A, ADJ>(a, dn, lane, R, r0, nr, slot);
           src_ready = true;
         }
       }
       const bool fwd = ADJ && ((flags >> 1) & 1);
-      if (fwd) compute_item<F, A, false>(d, cc, lane, nr, s_src, s_p, s_q, s_mat, acc, a.split);
-      else compute_item<F, A, ADJ>(d, cc, lane, nr, s_src, s_p, s_q, s_mat, acc, a.split);
+      if constexpr (LV) {
+        const auto srcf = [&](int t, int) -> cx<A> {
+          return up<A>(lvv[t < d.s_len0 ? d.s_off0 + t : d.s_off1 + (t - d.s_len0)]);
+        };
+        if (fwd) compute_item<F, A, false>(d, cc, lane, nr, srcf, s_p, s_q, s_mat, acc, a.split);
+        else compute_item<F, A, ADJ>(d, cc, lane, nr, srcf, s_p, s_q, s_mat, acc, a.split);
+      } else {
+        const auto srcf = [&](int t, int rr) -> cx<A> { return s_src[t * nr + rr]; };
+        if (fwd) compute_item<F, A, false>(d, cc, lane, nr, srcf, s_p, s_q, s_mat, acc, a.split);
+        else compute_item<F, A, ADJ>(d, cc, lane, nr, srcf, s_p, s_q, s_mat, acc, a.split);
+      }
       if (unit_end) {
         const double are = (flags & 1) ? a.alpha_re : 0.0, aim = (flags & 1) ? a.alpha_im : 0.0;
-        write_dst<V, A>(a, d, flags & 1, are, aim, lane, R, r0, nr, acc, a.split);
+        write_dst<V, A, LV>(a, d, flags & 1, are, aim, lane, R, r0, nr, acc, a.split, lvv);
       }
       wsync();
       have = nhave;
@@ -723,6 +751,14 @@ __device__ void prog_run(const StageArgs& a, const int32_t* steps, int s0, int s
     }
     __syncthreads();
   }
+  if constexpr (LV) {  // the program's rows of X and Y back to memory (every step has passed its barrier)
+    V* X = reinterpret_cast<V*>(a.buf[BUF_X]);
+    V* Y = reinterpret_cast<V*>(a.buf[BUF_Y]);
+    for (int e = tid; e < a.prows; e += kCompute * 64) {
+      X[static_cast<int64_t>(a.prow0 + e) * R + r0] = lvv[e];
+      Y[static_cast<int64_t>(a.prow0 + e) * R + r0] = lvv[a.prows + e];
+    }
+  }
 }
 
 // Stage launch: teams = waves; team t handles groups t, t + nteams, ... for RHS chunk `chunk`.
@@ -742,7 +778,7 @@ __global__ void __launch_bounds__(256) k_stage_pipe(StageArgs a, int ngroups, in
 }
 
 // Sweep program kernel: one workgroup per RHS chunk.
-template <class F, class V, class A, bool ADJ, bool NR1>
+template <class F, class V, class A, bool ADJ, bool NR1, bool LV>
 __global__ void __launch_bounds__(64 * prog_waves<F>()) k_program_pipe(StageArgs a, const int32_t* steps, int s0, int s1,
                                                                   int team_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -754,8 +790,9 @@ __global__ void __launch_bounds__(64 * prog_waves<F>()) k_program_pipe(StageArgs
   Unit* ring = reinterpret_cast<Unit*>(smem + static_cast<size_t>(prog_waves<F>()) * team_lds);
   int32_t* s_steps = reinterpret_cast<int32_t*>(ring + 3 * kDescMax);
   int* s_ctr = reinterpret_cast<int*>(s_steps + kStepInts * kStepWin);
-  prog_run<F, V, A, ADJ, NR1>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
-                              ring, s_ctr, a.R, r0, nr);
+  V* lvv = reinterpret_cast<V*>(s_ctr + 4);
+  prog_run<F, V, A, ADJ, NR1, LV>(a, steps, s0, s1, wave, lane, smem + static_cast<size_t>(wave) * team_lds, s_steps,
+                                  ring, s_ctr, lvv, a.R, r0, nr);
 }
 
 }  // namespace
@@ -763,6 +800,19 @@ __global__ void __launch_bounds__(64 * prog_waves<F>()) k_program_pipe(StageArgs
 int pipe_team_lds(int elt_acc, int elt_fac) {
   (void)elt_fac;
   return 256 * elt_acc + 1024 + kChunkW * 16;
+}
+
+// Per-wave LDS of a program with LDS-resident vectors (no source staging).
+int prog_team_lds_lv(int elt_fac) {
+  (void)elt_fac;
+  return 1024 + kChunkW * 16;
+}
+
+int prog_lds_rows_budget(int elt_fac, int elt_vec) {
+  const int waves = elt_fac == 8 ? prog_waves<float>() : prog_waves<double>();
+  const int base = prog_team_lds_lv(elt_fac) * waves + 3 * kDescMax * static_cast<int>(sizeof(Unit)) +
+                   kStepInts * static_cast<int>(sizeof(int32_t)) * kStepWin + 16;
+  return (160 * 1024 - base) / elt_vec;
 }
 
 template <class F, class V, class A>
@@ -788,21 +838,27 @@ static hipError_t launch_pipe(const StageArgs& a, int ngroups, int nchunks, bool
 template <class F, class V, class A>
 static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int s0, int s1, bool adjoint,
                                    hipStream_t s) {
-  const int lds1 = pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
+  const bool lv = a.lv_rows > 0;
+  const int lds1 = lv ? prog_team_lds_lv(static_cast<int>(sizeof(cx<F>)))
+                      : pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
   const dim3 grid(static_cast<unsigned>(a.nchunks));
-  const size_t lds =
-      static_cast<size_t>(lds1) * prog_waves<F>() + 3 * kDescMax * sizeof(Unit) + kStepInts * sizeof(int32_t) * kStepWin +
-      16;
+  const size_t lds = static_cast<size_t>(lds1) * prog_waves<F>() + 3 * kDescMax * sizeof(Unit) +
+                     kStepInts * sizeof(int32_t) * kStepWin + 16 + (lv ? sizeof(V) * a.lv_rows : 0);
   const dim3 block(64 * prog_waves<F>());
   const bool nr1 = a.rc == 1;
-  if (adjoint && nr1)
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
+  if (lv && !nr1) return hipErrorInvalidValue;
+  if (lv && adjoint)
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, true, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
+  else if (lv)
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, true, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
+  else if (adjoint && nr1)
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, true, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
   else if (adjoint)
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, true, false, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
   else if (nr1)
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, true>), grid, block, lds, s, a, steps, s0, s1, lds1);
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, true, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
   else
-    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
+    hipLaunchKernelGGL((k_program_pipe<F, V, A, false, false, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
   return hipGetLastError();
 }
 

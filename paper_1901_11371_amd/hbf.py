@@ -52,11 +52,14 @@ class HostPlan:
     """Host-side factorisation evaluated in FP64 on the CPU (construction
     checks; not a compute path of the library)."""
 
-    def __init__(self, curves, kappa, leaf, tol, prec="block", z=None, nthreads=0, lib=None):
+    def __init__(self, curves, kappa, leaf, tol, prec="block", z=None, nthreads=0, lib=None, dtype="c128"):
+        # dtype: the device storage type whose sweep schedule the plan mirrors
+        # (it sets which sweep programs keep their vectors in LDS); the host
+        # evaluation is FP64 either way
         self.lib = lib or _capi.load()
         cs, keep = _curve_struct(curves)
         self._keep = list(keep)
-        o, k2 = _opts("c128", prec, z, nthreads=nthreads)
+        o, k2 = _opts(dtype, prec, z, nthreads=nthreads)
         self._keep += k2
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_plan_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))

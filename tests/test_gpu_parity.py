@@ -127,6 +127,8 @@ TUNINGS = [
     {"sweep_rc1": 1},
     {"pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 1},
     {"pipe_max_r": 8, "sweep_pipe_max_r": 8},
+    {"prog_lds": 0},
+    {"prog_lds": 0, "prog_levels": 6},
 ]
 
 

@@ -34,8 +34,8 @@ def test_library_hankel_matches_oracle():
     assert np.max(np.abs(h - ref) / np.abs(ref)) < 5e-14
 
 
-def _plan(curves, tol=1e-6, prec="block", z=None):
-    return HostPlan(curves, KAPPA, 64, tol, prec=prec, z=z)
+def _plan(curves, tol=1e-6, prec="block", z=None, dtype="c128"):
+    return HostPlan(curves, KAPPA, 64, tol, prec=prec, z=z, dtype=dtype)
 
 
 def test_library_entries_match_oracle():
@@ -78,10 +78,14 @@ def test_host_plan_matvec_matches_dense(case, strip4096, spiral4096):
     assert np.linalg.norm(ya - refa) / np.linalg.norm(refa) < 1e-6
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("prec", ["block", "paper"])
-def test_host_plan_preconditioner_matches_dense(prec, spiral4096):
+def test_host_plan_preconditioner_matches_dense(prec, dtype, spiral4096):
+    """Both dtypes' sweep schedules: with complex64 storage the sweep
+    programs at this size keep their vectors and skeletons in LDS, so the
+    rows remapped into the LDS layout are checked here too."""
     c, A = spiral4096
-    p = _plan(c, prec=prec)
+    p = _plan(c, prec=prec, dtype=dtype)
     r = inputs.random_complex(4096, 22)
     f = (lambda v, adj=False: efie.precond_block_apply(A, v, 64, adjoint=adj)) if prec == "block" else \
         (lambda v, adj=False: efie.precond_paper_apply(A, v, adjoint=adj))
