@@ -38,11 +38,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the matvec at the default workload
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_stage_pipe_matvec_hbm_traffic_spiral_2p20_c64.txt")
 METRIC = "H-IDBF-LU apply GB/s; s/RHS at N=2^20 batched c64 vs plain c128, relres≤1e-6"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_digest():
+    """sha256 over the library's sources (name and contents, in name order):
+    identifies the build a set of hardware-counter readings was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1901_11371_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        path = os.path.join(d, name)
+        if os.path.isfile(path):
+            h.update(name.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per matvec launch from the committed counter summary, if its
+    readings were taken on these very sources (else None)."""
+    import re
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    src = re.search(r"sources sha256: ([0-9a-f]{64})", text)
+    tb = re.search(r"traffic bytes per launch: (\d+)", text)
+    if not src or not tb or src.group(1) != sources_digest():
+        return None
+    return int(tb.group(1))
 
 
 def main():
@@ -210,7 +243,9 @@ def main():
                   "precond_1rhs_gbs": (pc_fac + vec1) / t_pc / 1e9},
         "roofline": {"bound": "hbm", "kernel": "k_stage_pipe (single-RHS H-IDBF matvec stages)",
                      "achieved": round(mv_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(mv_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(mv_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic() if n == (1 << 20) else None,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "launches_per_apply": mv_launches,
                      "avg_launch_us": round(t_mv / mv_launches * 1e6, 3)},
         "tuned": tuned["params"] if tuned else None,

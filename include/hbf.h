@@ -175,7 +175,9 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *   "prog_pipe"     1 = pipelined wave teams inside the sweep programs,
  *   "r1_kernel"     1 = register-streaming kernel with LDS atomics for one-RHS
  *                   stages (when pipe_max_r is 0),
- *   "r1_max_blocks" persistent grid size (workgroups) of the one-RHS kernels,
+ *   "r1_max_blocks" persistent grid size (workgroups) of the pipelined and
+ *                   one-RHS stage kernels; 0 = as many as the device holds at
+ *                   once,
  *   "wave_units"    1 = one wave per unit for two-RHS stages,
  *   "lane_split"    1 = in the pipelined kernels, up to 32 lanes share the
  *                   dot product of one output of a unit with few outputs,
@@ -185,6 +187,8 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *                   use the pipelined kernel with one RHS per workgroup chunk,
  *   "prog_lds"      1 = sweep programs whose vectors fit keep them in LDS
  *                   (default 1),
+ *   "mv_direct"     1 = matvec stages of single-unit groups run over copies of
+ *                   their unit descriptors in launch order (default 1),
  *   "use_graphs"    1 = replay the preconditioner sweeps from HIP graphs.
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);

@@ -58,6 +58,7 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_gunits);
   dfree(c->d_steps);
   dfree(c->d_punits);
+  dfree(c->d_lunits);
   dfree(c->d_arena);
   dfree(c->d_vin);
   dfree(c->d_vout);
@@ -308,7 +309,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       continue;
     }
     StageArgs a;
-    a.units = c->d_units;
+    a.units = l.ucopy ? c->d_lunits : c->d_units;
     a.gofs = c->d_gofs;
     a.gunits = c->d_gunits;
     a.fac = c->d_fac;
@@ -401,8 +402,10 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
 
 hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s) {
   hipError_t e;
-  if (!adjoint) e = run_launches(c, c->P.mv_fwd, false, xin, yout, R, vec_c128, 1.0, 0.0, s);
-  else e = run_launches(c, c->P.mv_adj, true, yout, xin, R, vec_c128, 1.0, 0.0, s);
+  const std::vector<Launch>& fw = c->mv_direct ? c->mv_fwd : c->P.mv_fwd;
+  const std::vector<Launch>& bw = c->mv_direct ? c->mv_adj : c->P.mv_adj;
+  if (!adjoint) e = run_launches(c, fw, false, xin, yout, R, vec_c128, 1.0, 0.0, s);
+  else e = run_launches(c, bw, true, yout, xin, R, vec_c128, 1.0, 0.0, s);
   if (e != hipSuccess) return fail(HBF_EHIP, std::string("matvec launch: ") + hipGetErrorString(e));
   return HBF_OK;
 }
@@ -565,7 +568,28 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     hip_check(hipMemcpy(c->d_gunits, P.group_units.data(), P.group_units.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice),
               "groups");
+    {
+      // Matvec launches whose groups are single units run direct over copies
+      // of their unit descriptors in launch order: a team finds each item's
+      // descriptor without reading the group tables first.
+      std::vector<Unit> lu;
+      c->mv_fwd = P.mv_fwd;
+      c->mv_adj = P.mv_adj;
+      for (auto* L : {&c->mv_fwd, &c->mv_adj})
+        for (Launch& l : *L) {
+          if (l.direct || !l.single) continue;
+          const int32_t base = static_cast<int32_t>(lu.size());
+          for (int32_t g = l.first; g < l.first + l.count; ++g) lu.push_back(P.units[P.group_units[P.group_off[g]]]);
+          l.first = base;
+          l.direct = 1;
+          l.ucopy = 1;
+        }
+      dmalloc(&c->d_lunits, std::max<size_t>(lu.size(), 1) * sizeof(Unit), "units");
+      if (!lu.empty())
+        hip_check(hipMemcpy(c->d_lunits, lu.data(), lu.size() * sizeof(Unit), hipMemcpyHostToDevice), "units");
+    }
     rebuild_sweeps(c.get(), c->S.prog_levels);
+    prepare_launch_shapes();
     const size_t R = static_cast<size_t>(c->max_nrhs);
     const size_t vbytes = static_cast<size_t>(N) * R * 16;
     dmalloc(&c->d_arena, static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16, "arena");
@@ -740,6 +764,11 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     }
     return HBF_OK;
   }
+  if (k == "mv_direct") {
+    if (value != 0 && value != 1) return fail(HBF_EINVAL, "hbf_tune: mv_direct must be 0 or 1");
+    c->mv_direct = value != 0;
+    return HBF_OK;
+  }
   if (k == "prog_lds") {
     (void)hipDeviceSynchronize();
     free_graphs(c);
@@ -780,7 +809,7 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
   }
   if (k == "use_graphs") { c->use_graphs = value != 0; free_graphs(c); return HBF_OK; }
   if (k == "r1_max_blocks") {
-    if (value < 1 || value > (1 << 20)) return fail(HBF_EINVAL, "hbf_tune: r1_max_blocks out of range");
+    if (value < 0 || value > (1 << 20)) return fail(HBF_EINVAL, "hbf_tune: r1_max_blocks out of range");
     c->r1_max_blocks = static_cast<int>(value);
     free_graphs(c);
     return HBF_OK;

@@ -28,8 +28,9 @@ struct hbf_ctx {
   bool sweep_rc1 = false;      // sweep stage launches above pipe_max_r: pipelined kernel, one RHS per chunk
   int sweep_pipe_max_r = 4;    // pipe_max_r for the sweeps' stage launches
   bool prog_lds = true;        // sweep programs keep their vectors in LDS where they fit
+  bool mv_direct = true;       // matvec launches of single-unit groups run direct over unit copies
   int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
-  int r1_max_blocks = 2048;    // persistent grid size of that kernel
+  int r1_max_blocks = 0;       // persistent grid size of the stage kernels (0: resident capacity)
 
   // device memory
   void* d_fac = nullptr;       // factors + leaf inverses (storage dtype)
@@ -39,6 +40,8 @@ struct hbf_ctx {
   int32_t* d_gunits = nullptr;
   int32_t* d_steps = nullptr;  // program steps of the sweeps
   hbf::Unit* d_punits = nullptr;  // unit copies of the programs with LDS-resident vectors
+  hbf::Unit* d_lunits = nullptr;  // launch-order unit copies of the direct matvec launches
+  std::vector<hbf::Launch> mv_fwd, mv_adj;  // matvec schedules as launched (mv_direct)
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
   void* d_vin = nullptr;       // internal-layout vectors, N x max_nrhs x 16 bytes each
   void* d_vout = nullptr;

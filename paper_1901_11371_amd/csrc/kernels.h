@@ -54,6 +54,8 @@ int prog_team_lds_lv(int elt_fac);
 // Largest vector footprint (rows of elt_vec bytes) a sweep program can keep in
 // LDS next to its staging areas.
 int prog_lds_rows_budget(int elt_fac, int elt_vec);
+// Resident-capacity queries of the stage kernels (call outside stream capture).
+void prepare_launch_shapes();
 hipError_t launch_pipe_c64(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s);
 hipError_t launch_pipe_c128(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s);
 hipError_t launch_pipe_c64_hi(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks,

@@ -7,6 +7,11 @@
 // flight, and the descriptor of the unit after that is fetched one step
 // earlier still.  Used for the matvec and sweep stages with few right-hand
 // sides per team and for the sweep programs.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.h"
 
 namespace hbf {
@@ -412,6 +417,15 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
   UDesc d = read_desc<ADJ, F>(unit_of(cur.q));
   Slot<V> slot;
   issue<F, V, A, ADJ>(a, d, 0, lane, R, r0, nr, slot);
+  // Direct launches: the descriptor of the team's next unit is fetched one
+  // unit ahead by a vector load (lane l < 16 holds its dword l), so moving to
+  // a unit waits on no scalar load; vector loads complete in order, so the
+  // wait for an item's data never waits on this one.
+  int vdesc = 0;
+  auto load_vdesc = [&](int g) {
+    if (g < ngroups && lane < 16) vdesc = reinterpret_cast<const int*>(a.units + first_group + g)[lane];
+  };
+  if (a.direct) load_vdesc(gi + nteams);
 
   cx<A> acc[kOpt];
 #pragma unroll
@@ -441,8 +455,20 @@ __device__ void team_run(const StageArgs& a, int first_group, int ngroups, int t
     }
     UDesc dn = d;
     if (nxt.q >= 0) {
-      if (nxt.c == 0) dn = read_desc<ADJ, F>(unit_of(nxt.q));
+      if (nxt.c == 0) {
+        if (a.direct) {
+          int w[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) w[i] = __builtin_amdgcn_readlane(vdesc, i);
+          Unit u;
+          __builtin_memcpy(&u, w, sizeof(Unit));
+          dn = read_desc<ADJ, F>(&u);
+        } else {
+          dn = read_desc<ADJ, F>(unit_of(nxt.q));
+        }
+      }
       issue<F, V, A, ADJ>(a, dn, nxt.c, lane, R, r0, nr, slot);
+      if (a.direct && nxt.c == 0) load_vdesc(nxt.g + nteams);
     }
     const auto srcf = [&](int t, int rr) -> cx<A> { return s_src[t * nr + rr]; };
     compute_item<F, A, ADJ>(d, cur.c, lane, nr, srcf, s_p, s_q, s_mat, acc, (a.direct || a.single) && a.split);
@@ -815,23 +841,66 @@ int prog_lds_rows_budget(int elt_fac, int elt_vec) {
   return (160 * 1024 - base) / elt_vec;
 }
 
+// Workgroups of `kernel` the device holds at once (every CU filled to the
+// occupancy its registers and `lds` bytes of LDS allow).
+static int resident_blocks(const void* kernel, int block, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(kernel, lds, block, dev);
+  std::lock_guard<std::mutex> lk(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int n = per_cu * cus;
+  cache[key] = n;
+  return n;
+}
+
+// max_blocks > 0 caps the grid's x size; 0 sizes it to the resident capacity
+// (the teams are persistent: a second partial round of workgroups would only
+// start once the first round has finished its share).
+template <class F, class V, class A>
+static void (*pipe_kernel(bool adjoint, bool nr1))(StageArgs, int, int) {
+  return adjoint ? (nr1 ? k_stage_pipe<F, V, A, true, true> : k_stage_pipe<F, V, A, true, false>)
+                 : (nr1 ? k_stage_pipe<F, V, A, false, true> : k_stage_pipe<F, V, A, false, false>);
+}
+
+template <class F, class V, class A>
+static int pipe_lds1() {
+  return pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
+}
+
+// Occupancy queries of every stage-kernel variant, made outside any stream
+// capture (a query is not a stream operation, but it need not run while a
+// graph is being recorded).
+template <class F, class V, class A>
+static void prepare_pipe() {
+  for (int v = 0; v < 4; ++v)
+    resident_blocks(reinterpret_cast<const void*>(pipe_kernel<F, V, A>(v & 1, v >> 1)), 256,
+                    static_cast<size_t>(pipe_lds1<F, V, A>()) * 4);
+}
+
 template <class F, class V, class A>
 static hipError_t launch_pipe(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks,
                               hipStream_t s) {
-  const int lds1 = pipe_team_lds(static_cast<int>(sizeof(cx<A>)), static_cast<int>(sizeof(cx<F>)));
+  const int lds1 = pipe_lds1<F, V, A>();
+  const bool nr1 = a.rc == 1;
+  void (*kern)(StageArgs, int, int) = pipe_kernel<F, V, A>(adjoint, nr1);
+  int cap = max_blocks;
+  if (cap <= 0) {
+    const int res = resident_blocks(reinterpret_cast<const void*>(kern), 256, static_cast<size_t>(lds1) * 4);
+    cap = res > 0 ? std::max(1, res / std::max(1, nchunks)) : 2048;
+  }
   int bx = (ngroups + 3) / 4;
-  if (bx > max_blocks) bx = max_blocks;
+  if (bx > cap) bx = cap;
   if (bx < 1) bx = 1;
   const dim3 grid(static_cast<unsigned>(bx), static_cast<unsigned>(nchunks));
-  const bool nr1 = a.rc == 1;
-  if (adjoint && nr1)
-    hipLaunchKernelGGL((k_stage_pipe<F, V, A, true, true>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
-  else if (adjoint)
-    hipLaunchKernelGGL((k_stage_pipe<F, V, A, true, false>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
-  else if (nr1)
-    hipLaunchKernelGGL((k_stage_pipe<F, V, A, false, true>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
-  else
-    hipLaunchKernelGGL((k_stage_pipe<F, V, A, false, false>), grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
+  hipLaunchKernelGGL(kern, grid, dim3(256), lds1 * 4, s, a, ngroups, lds1);
   return hipGetLastError();
 }
 
@@ -860,6 +929,12 @@ static hipError_t launch_prog_pipe(const StageArgs& a, const int32_t* steps, int
   else
     hipLaunchKernelGGL((k_program_pipe<F, V, A, false, false, false>), grid, block, lds, s, a, steps, s0, s1, lds1);
   return hipGetLastError();
+}
+
+void prepare_launch_shapes() {
+  prepare_pipe<float, cf, float>();
+  prepare_pipe<double, cd, double>();
+  prepare_pipe<float, cd, double>();
 }
 
 hipError_t launch_pipe_c64(const StageArgs& a, int ngroups, int nchunks, bool adjoint, int max_blocks, hipStream_t s) {

@@ -240,7 +240,7 @@ hipError_t launch_r1(const StageArgs& a, int ngroups, bool adjoint, int max_bloc
   const size_t per_wave = 2 * M * sizeof(A) + 2 * M * sizeof(A) + 4 * M;
   const size_t lds = per_wave * kWaves;
   int blocks = (ngroups + kWaves - 1) / kWaves;
-  if (blocks > max_blocks) blocks = max_blocks;
+  if (blocks > (max_blocks > 0 ? max_blocks : 2048)) blocks = max_blocks > 0 ? max_blocks : 2048;
   if (blocks < 1) blocks = 1;
   if (adjoint) hipLaunchKernelGGL((k_stage_r1<F, V, A, true>), dim3(blocks), dim3(64 * kWaves), lds, s, a, ngroups);
   else hipLaunchKernelGGL((k_stage_r1<F, V, A, false>), dim3(blocks), dim3(64 * kWaves), lds, s, a, ngroups);

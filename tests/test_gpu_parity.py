@@ -129,6 +129,10 @@ TUNINGS = [
     {"pipe_max_r": 8, "sweep_pipe_max_r": 8},
     {"prog_lds": 0},
     {"prog_lds": 0, "prog_levels": 6},
+    {"mv_direct": 0},
+    {"mv_direct": 0, "lane_split": 0},
+    {"r1_max_blocks": 2048},
+    {"r1_max_blocks": 3, "sweep_pipe_max_r": 8},
 ]
 
 
