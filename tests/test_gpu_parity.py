@@ -136,26 +136,39 @@ TUNINGS = [
 ]
 
 
+@pytest.fixture(scope="module")
+def tuning_refs(spiral):
+    """Oracle matvec and preconditioner of the five seeded RHS the tuning
+    tests share (forward and adjoint), computed once."""
+    c, A = spiral
+    R = inputs.random_complex((5, 4096), 35)
+    refs = {}
+    for adj in (False, True):
+        ref = ((A.conj().T if adj else A) @ R.T).T
+        refz = np.stack([efie.precond_block_apply(A, R[i], 64, adjoint=adj) for i in range(5)])
+        refs[adj] = (ref, refz)
+    return R, refs
+
+
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: ",".join(f"{k}={v}" for k, v in t.items()))
-def test_execution_parameters_keep_results(torch, spiral, tuning):
+def test_execution_parameters_keep_results(torch, spiral, tuning_refs, tuning):
     """Every execution parameter the autotuner may pick gives the oracle's
     matvec and preconditioner (forward and adjoint, 1 and 5 RHS)."""
     c, A = spiral
+    R, refs = tuning_refs
     _say(f"[tuning] {tuning}")
     ctx = _ctx(c, "c64")
     for k, v in tuning.items():
         ctx.tune(k, v)
-    R = inputs.random_complex((5, 4096), 35)
     Rt = torch.tensor(R, dtype=torch.complex64, device="cuda")
     for adj in (False, True):
+        ref, refz = refs[adj]
         Y = ctx.matvec(Rt, adjoint=adj).cpu().numpy()
-        ref = (A.conj().T if adj else A) @ R.T
-        err = _rel(Y, ref.T)
+        err = _rel(Y, ref)
         y1 = ctx.matvec(Rt[2].contiguous(), adjoint=adj).cpu().numpy()
         _say(f"  matvec adjoint={adj} rel err {err:.3e}")
         assert err < 5e-6 and _rel(y1, Y[2]) < 1e-5
         Z = ctx.precond(Rt, adjoint=adj).cpu().numpy()
-        refz = np.stack([efie.precond_block_apply(A, R[i], 64, adjoint=adj) for i in range(5)])
         errz = _rel(Z, refz)
         z1 = ctx.precond(Rt[2].contiguous(), adjoint=adj).cpu().numpy()
         _say(f"  precond adjoint={adj} rel err {errz:.3e}")
