@@ -181,13 +181,14 @@ __device__ __forceinline__ void issue(const StageArgs& a, const UDesc& d, int c,
 template <class F, class V, class A, bool SRC = true>
 __device__ __forceinline__ void commit(const UDesc& d, int c, int lane, int nr, const Slot<V>& slot, cx<A>* s_src,
                                        uint8_t* s_p, uint8_t* s_q, u32x4* s_m4) {
+  // The source and matrix staging areas have fixed sizes (64 kSrcPL entries,
+  // kChunkW words), so every lane writes all of its slots: entries past the
+  // item's data hold stale values that nothing reads, and no exec-masked
+  // block per element is needed.
   if (c == 0) {
     if constexpr (SRC) {
 #pragma unroll
-      for (int j = 0; j < kSrcPL; ++j) {
-        const int e = lane + 64 * j;
-        if (e < d.n_src * nr) s_src[e] = up<A>(slot.sv[j]);
-      }
+      for (int j = 0; j < kSrcPL; ++j) s_src[lane + 64 * j] = up<A>(slot.sv[j]);
     }
 #pragma unroll
     for (int j = 0; j < kPermPL; ++j) {
@@ -200,10 +201,7 @@ __device__ __forceinline__ void commit(const UDesc& d, int c, int lane, int nr, 
     }
   }
 #pragma unroll
-  for (int j = 0; j < kPW; ++j) {
-    const int w = c * kChunkW + lane + 64 * j;
-    if (w < d.nwords) s_m4[lane + 64 * j] = slot.mw[j];
-  }
+  for (int j = 0; j < kPW; ++j) s_m4[lane + 64 * j] = slot.mw[j];
 }
 
 // Accumulate one item (a matrix chunk of one unit) into the lane's outputs.
