@@ -15,7 +15,8 @@ approximates, in complex128 with NumPy/SciPy:
   (Sec. 3.1, the definitions of L~ and U~, and the split system solved with
   them), in two readings: the paper's point-wise triangular parts, and the
   block form whose leaf blocks are the exact n0 x n0 diagonal blocks;
-* a restarted, right-preconditioned GMRES used only for iteration counts;
+* a restarted, right-preconditioned GMRES and TFQMR (the paper's Krylov
+  method) used for iteration counts;
 * a far-field objective and its gradient through the adjoint system.
 
 The Hankel function is SciPy's ``hankel2`` (AMOS); the GPU library carries
@@ -278,6 +279,66 @@ def gmres(apply_A, apply_Minv, b, tol=1e-6, restart=50, maxiter=1000):
         x = x + apply_Minv(V[:, :j_done] @ y)
         r = b - apply_A(x)
     return x, it, hist
+
+
+def tfqmr(apply_A, apply_Minv, b, tol=1e-6, maxiter=1000):
+    """Transpose-free QMR (Freund, SIAM J. Sci. Comput. 14, 1993), the Krylov
+    method of the paper's experiments (Sec. 4), on the right-preconditioned
+    system A M^{-1} u = b with x0 = 0, x = M^{-1} u, shadow vector r~ = b.
+    Each iteration is two half steps with one product by A M^{-1} each; the
+    iteration stops when the quasi-residual bound tau sqrt(half steps + 1)
+    falls to tol ||b|| (and the true residual confirms it).
+    Returns (x, iterations, bound_history)."""
+    bnorm = np.linalg.norm(b)
+    op = lambda v: apply_A(apply_Minv(v))
+    u = np.zeros_like(b)           # solution of the preconditioned system
+    w = b.copy()
+    y1 = b.copy()
+    rt = b.copy()
+    Ay1 = op(y1)
+    v = Ay1.copy()
+    d = np.zeros_like(b)
+    tau = bnorm
+    theta = 0.0
+    eta = 0.0
+    rho = np.vdot(rt, w)
+    hist = []
+    half = 0
+
+    def half_step(y, Ay):
+        nonlocal w, d, theta, tau, eta, u, half
+        w = w - alpha * Ay
+        d = y + (theta ** 2 * eta / alpha) * d
+        theta = np.linalg.norm(w) / tau
+        c = 1.0 / math.sqrt(1.0 + theta ** 2)
+        tau = tau * theta * c
+        eta = c ** 2 * alpha
+        u = u + eta * d
+        half += 1
+        hist.append(tau * math.sqrt(half + 1) / bnorm)
+        if hist[-1] <= tol:
+            x = apply_Minv(u)
+            return np.linalg.norm(b - apply_A(x)) <= tol * bnorm
+        return False
+
+    for it in range(maxiter):
+        sigma = np.vdot(rt, v)
+        if sigma == 0 or rho == 0:
+            break
+        alpha = rho / sigma
+        y2 = y1 - alpha * v
+        if half_step(y1, Ay1):
+            return apply_Minv(u), it + 1, hist
+        Ay2 = op(y2)
+        if half_step(y2, Ay2):
+            return apply_Minv(u), it + 1, hist
+        rho_new = np.vdot(rt, w)
+        beta = rho_new / rho
+        rho = rho_new
+        y1 = w + beta * y2
+        Ay1 = op(y1)
+        v = Ay1 + beta * (Ay2 + beta * v)
+    return apply_Minv(u), maxiter, hist
 
 
 # ---------------------------------------------------------------------------
