@@ -89,10 +89,12 @@ def main():
     ap.add_argument("--no-srhs", action="store_true", help="skip the semicircle seconds-per-RHS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch"],
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch", "matvec_batch"],
                     help="matvec / precond: only the single-RHS apply loop; precond_batch: the nrhs-RHS "
                          "preconditioner loop with the autotuned parameters (for profiling)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--params", default=None,
+                    help="JSON object of execution parameters to set instead of autotuning (profiling modes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; multi-GPU execution is not part of this library "
@@ -134,6 +136,9 @@ def main():
         ev1.synchronize()
         return ev0.elapsed_time(ev1) / 1e3 / reps
 
+    if args.params:
+        for k, v in json.loads(args.params).items():
+            ctx.tune(k, v)
     x1 = torch.tensor(inputs.random_complex(n, 7), dtype=torch.complex64, device=dev)
     if args.mode == "matvec":
         # a plain copy of known size first: the calibration kernel for the HBM counters
@@ -150,8 +155,14 @@ def main():
         print(json.dumps({"mode": "matvec", "ms": t_mv * 1e3, "gbs": (mv_fac + vec1) / t_mv / 1e9,
                           "launches": mv_launches, "avg_launch_us": t_mv / mv_launches * 1e6}))
         return
+    if args.mode == "matvec_batch":
+        XB = torch.tensor(inputs.random_complex((R, n), 8), dtype=torch.complex64, device=dev)
+        t_mb = timed_loop(lambda: ctx.matvec(XB), max(2, args.reps // 4))
+        print(json.dumps({"mode": "matvec_batch", "nrhs": R, "ms": t_mb * 1e3}))
+        return
     if args.mode == "precond_batch":
-        autotune.apply(ctx, R) or autotune.autotune(ctx, nrhs=R, reps=1)
+        if not args.params:
+            autotune.apply(ctx, R) or autotune.autotune(ctx, nrhs=R, reps=1)
         XB = torch.tensor(inputs.random_complex((R, n), 8), dtype=torch.complex64, device=dev)
         t_pb = timed_loop(lambda: ctx.precond(XB), max(2, args.reps // 10))
         print(json.dumps({"mode": "precond_batch", "nrhs": R, "ms": t_pb * 1e3}))
@@ -306,32 +317,73 @@ def seconds_per_rhs(n, R, m):
     return out
 
 
-def cpu_baseline(curves, x_gpu, b, mv_bytes, nrows=96):
-    """The CPU oracle on a bounded sample: exact rows of A x (matrix-free FP64,
-    SciPy Hankel) for a seeded sample of rows of the spiral, scaled to one full
-    apply.  As a by-product it reports the exact-operator residual of the GPU
-    spiral iterate on the sampled rows."""
+def _oracle_rows(args):
+    """Worker: exact rows of A x with the oracle (one process per core)."""
+    rows, x, rho, w, kappa = args
+    from oracle import efie
+    return efie.exact_rows_matvec(rows, x, rho, w, kappa, chunk=8)
+
+
+def cpu_baseline(curves, x_gpu, b, mv_bytes, rows_per_core=12):
+    """The CPU oracle as it stands, on the host's cores, on a bounded sample.
+
+    * Matrix-free exact rows of A x (FP64, SciPy Hankel) for a seeded sample
+      of rows of the spiral, one process per core, scaled by N / rows to one
+      full apply and expressed in the H-IDBF matvec's algorithmic GB/s (the
+      value).  As a by-product: the exact-operator residual of the GPU
+      spiral iterate on the sampled rows.
+    * The dense path at N = 4096 (the plain-strip workload): Z assembly,
+      GEMV and LU factorisation + solve (NumPy / SciPy with the BLAS's own
+      threads)."""
+    import multiprocessing as mp
+
     import numpy as np
 
     from oracle import efie
     from paper_1901_11371_amd import inputs
+    cores = os.cpu_count() or 1
     rho, w = efie.segments(curves.xy, curves.node_off)
     n = rho.shape[0]
     rng = np.random.default_rng(inputs.SEED_BASE + 2)
+    nrows = rows_per_core * cores
     rows = np.sort(rng.choice(n, nrows, replace=False))
+    x = x_gpu.astype(np.complex128)
+    parts = np.array_split(rows, cores)
     t0 = time.perf_counter()
-    ax = efie.exact_rows_matvec(rows, x_gpu.astype(np.complex128), rho, w, inputs.KAPPA, chunk=8)
+    with mp.get_context("spawn").Pool(cores) as pool:
+        outs = pool.map(_oracle_rows, [(p, x, rho, w, inputs.KAPPA) for p in parts])
     t = time.perf_counter() - t0
-    t_full = t * n / len(rows)
+    ax = np.concatenate(outs)
+    t_full = t * n / nrows
     res = np.linalg.norm(b[rows] - ax) / np.linalg.norm(b[rows])
-    log(f"[bench] oracle: {len(rows)} exact rows in {t:.1f}s -> full apply {t_full:.0f}s (extrapolated); "
-        f"sampled exact residual of the GPU iterate {res:.2e}")
-    return {"value": round(mv_bytes / t_full / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(rows)} seeded rows of the exact matrix-free FP64 product A x at N={n} "
-                      f"({t:.1f} s, one thread), scaled by N/{len(rows)} to one apply; GB/s = the "
-                      f"H-IDBF matvec's algorithmic bytes over that time",
+    log(f"[bench] oracle: {nrows} exact rows on {cores} cores in {t:.1f}s -> full apply {t_full:.0f}s "
+        f"(extrapolated); sampled exact residual of the GPU iterate {res:.2e}")
+    # dense path at N = 4096 (plain strip)
+    wl = inputs.workload(0)
+    rho4, w4 = efie.segments(wl.curves.xy, wl.curves.node_off)
+    t0 = time.perf_counter()
+    A4 = efie.dense_A(rho4, w4, inputs.KAPPA)
+    t_asm = time.perf_counter() - t0
+    b4 = inputs.plane_wave_rhs(wl.curves, wl.angles)[0]
+    t0 = time.perf_counter()
+    for _ in range(10):
+        y4 = efie.matvec(A4, b4)
+    t_gemv = (time.perf_counter() - t0) / 10
+    t0 = time.perf_counter()
+    x4 = efie.lu_solve(A4, b4)
+    t_lu = time.perf_counter() - t0
+    rr = float(efie.relres(A4, x4, b4))
+    log(f"[bench] oracle dense N=4096: assembly {t_asm:.2f}s, GEMV {t_gemv*1e3:.1f} ms, LU solve {t_lu:.2f}s "
+        f"(relres {rr:.1e})")
+    del y4
+    return {"value": round(mv_bytes / t_full / 1e9, 6), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nrows} seeded rows of the exact matrix-free FP64 product A x at N={n}, one process per "
+                      f"core ({cores}), {t:.1f} s, scaled by N/{nrows} to one apply; GB/s = the H-IDBF matvec's "
+                      f"algorithmic bytes over that time",
             "seconds_per_apply_extrapolated": t_full,
-            "gpu_iterate_sampled_exact_relres": float(res)}
+            "gpu_iterate_sampled_exact_relres": float(res),
+            "dense_4096": {"assembly_s": t_asm, "gemv_s": t_gemv, "lu_solve_s": t_lu, "relres": rr,
+                           "workload": "plain strip N=4096, complex128, NumPy/SciPy BLAS threads"}}
 
 
 if __name__ == "__main__":

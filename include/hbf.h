@@ -85,6 +85,9 @@ typedef struct {
                          the host construction; 0: no caching (a cache hit is still used) */
 } hbf_build_opts;
 
+/* Krylov method of the inner solves. */
+typedef enum { HBF_GMRES = 0, HBF_TFQMR = 1 } hbf_method;
+
 typedef struct {
   double tol;          /* relative residual target ||b - A x|| / ||b|| (<= 0: 1e-6) */
   int32_t restart;     /* GMRES restart length m (<= 0: build-time value; capped by it) */
@@ -93,11 +96,15 @@ typedef struct {
   int32_t mixed;       /* 1: inner GMRES in complex64 with FP32 factors and FP64 Arnoldi,
                           outer FP64 residual + refinement; 0: everything in the ctx dtype */
   int32_t x0_given;    /* 1: x holds the initial guess on entry; 0: start from x = 0 */
-  double inner_tol;    /* relative tolerance of each inner GMRES (<= 0: 1e-4 when mixed) */
+  double inner_tol;    /* relative tolerance of each inner cycle (<= 0: 1e-4 when mixed) */
+  int32_t method;      /* hbf_method: restarted GMRES(m) (default) or TFQMR (the paper's solver,
+                          Sec. 4; no Krylov basis, two matvecs and preconditioner applications per
+                          iteration, `restart` unused) */
 } hbf_solve_opts;
 
 typedef struct {
-  int32_t iters;        /* inner GMRES iterations (all cycles) */
+  int32_t iters;        /* inner iterations, all cycles (GMRES: Arnoldi steps; TFQMR: iterations of
+                           two operator applications each) */
   int32_t refinements;  /* outer refinement steps */
   int32_t converged;    /* 1 if relres <= tol */
   double relres;        /* final ||b - A x|| / ||b||, FP64 with the stored operator */
@@ -122,6 +129,7 @@ typedef struct {
   int64_t apply_bytes_matvec;    /* y = A x (Algorithm 2) */
   int64_t apply_bytes_precond;   /* z = P^{-1} r (both sweeps, and s = D t in the block reading) */
   int64_t launches_matvec;       /* kernel launches of one matvec */
+  int64_t arena_rows;            /* rows of skeleton vectors (sum of all ID ranks) per RHS */
 } hbf_stats_t;
 
 /* Build the H-IDBF of A = Z + diag(z) for the curve at wavenumber `kappa`
@@ -166,6 +174,15 @@ hbf_status hbf_solve(hbf_ctx* ctx, const void* b, void* x, int32_t nrhs, hbf_dty
 hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrhs, hbf_dtype io,
                              const hbf_solve_opts* opts, hbf_solve_info* info, void* stream);
 
+/* grad_z = -sum_r lam_r (.) conj(x_r): the gradient of a real objective with
+ * respect to the per-unknown impedance z of A = Z + diag(z), given the forward
+ * solutions x = A^{-1} b and the adjoint solutions lam = A^{-H} g (A depends
+ * on z only through its diagonal; Sec. 3.1 defines the system).  lam and x are
+ * device (nrhs, N) arrays of dtype io; grad_z is a device array of N entries
+ * of dtype io, overwritten.  Stream-ordered and asynchronous. */
+hbf_status hbf_impedance_grad(hbf_ctx* ctx, const void* lam, const void* x, int32_t nrhs, hbf_dtype io,
+                              void* grad_z, void* stream);
+
 /* Set an execution parameter of the context (used by the autotuner; results
  * do not depend on them beyond rounding):
  *   "prog_levels"   subtrees of <= 2^value leaves are swept by one workgroup
@@ -173,8 +190,6 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *   "pipe_max_r"    stage launches with nrhs <= value use pipelined wave teams
  *                   (default 4),
  *   "prog_pipe"     1 = pipelined wave teams inside the sweep programs,
- *   "r1_kernel"     1 = register-streaming kernel with LDS atomics for one-RHS
- *                   stages (when pipe_max_r is 0),
  *   "r1_max_blocks" persistent grid size (workgroups) of the pipelined and
  *                   one-RHS stage kernels; 0 = as many as the device holds at
  *                   once,
@@ -189,7 +204,11 @@ hbf_status hbf_solve_adjoint(hbf_ctx* ctx, const void* g, void* lam, int32_t nrh
  *                   (default 1),
  *   "mv_direct"     1 = matvec stages of single-unit groups run over copies of
  *                   their unit descriptors in launch order (default 1),
- *   "use_graphs"    1 = replay the preconditioner sweeps from HIP graphs.
+ *   "use_graphs"    1 = replay the preconditioner sweeps and the solvers' steps
+ *                   from HIP graphs,
+ *   "mfma"          1 = complex64 stage launches with nrhs >= mfma_min_r run
+ *                   as complex GEMMs on the FP32 matrix cores (default 1),
+ *   "mfma_min_r"    smallest nrhs for the matrix-core stage launches (default 8).
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);
 

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libhbf.so")
 HBF_OK, HBF_NOCONV, HBF_EINVAL, HBF_ENOMEM, HBF_EHIP, HBF_ESINGULAR, HBF_ESTATE = 0, 1, -1, -2, -3, -4, -5
 HBF_C64, HBF_C128 = 0, 1
 HBF_PREC_BLOCK_LU, HBF_PREC_PAPER_TRI, HBF_PREC_NONE = 0, 1, 2
+HBF_GMRES, HBF_TFQMR = 0, 1
 
 
 class Curve(C.Structure):
@@ -26,7 +27,7 @@ class BuildOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32),
                 ("max_refine", C.c_int32), ("mixed", C.c_int32), ("x0_given", C.c_int32),
-                ("inner_tol", C.c_double)]
+                ("inner_tol", C.c_double), ("method", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -40,7 +41,8 @@ class Stats(C.Structure):
                 ("bytes_butterfly", C.c_int64), ("bytes_dense", C.c_int64), ("bytes_index", C.c_int64),
                 ("bytes_precond", C.c_int64), ("bytes_workspace", C.c_int64), ("build_seconds", C.c_double),
                 ("scale_re", C.c_double), ("scale_im", C.c_double), ("apply_bytes_matvec", C.c_int64),
-                ("apply_bytes_precond", C.c_int64), ("launches_matvec", C.c_int64)]
+                ("apply_bytes_precond", C.c_int64), ("launches_matvec", C.c_int64),
+                ("arena_rows", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -58,6 +60,8 @@ SIGNATURES = {
                             C.POINTER(SolveInfo), C.c_void_p]),
     "hbf_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int,
                                     C.POINTER(SolveOpts), C.POINTER(SolveInfo), C.c_void_p]),
+    "hbf_impedance_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int, C.c_void_p,
+                                     C.c_void_p]),
     "hbf_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "hbf_tune": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "hbf_size": (C.c_int64, [C.c_void_p]),

@@ -45,6 +45,8 @@ void dfree(void* p) {
 void free_graphs(hbf_ctx* c) {
   for (auto& kv : c->pc_graphs) (void)hipGraphExecDestroy(kv.second);
   c->pc_graphs.clear();
+  for (auto& kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->step_graphs.clear();
 }
 
 void free_device(hbf_ctx* c) {
@@ -71,6 +73,13 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_x64);
   dfree(c->d_red);
   dfree(c->d_small);
+  if (c->h_flags) (void)hipHostFree(c->h_flags);
+  c->h_flags = nullptr;
+  for (auto& e : c->ev_step)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   c->d_fac = c->d_arena = c->d_vin = c->d_vout = c->d_u = c->d_t = nullptr;
   c->d_krylov = c->d_w = c->d_x64 = nullptr;
 }
@@ -252,7 +261,8 @@ void rebuild_sweeps(hbf_ctx* c, int prog_levels) {
 }
 
 hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
-                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep) {
+                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep, void* arena) {
+  void* const ar = arena ? arena : c->d_arena;
   const size_t szA = (vec_c128 || c->dtype == HBF_C128) ? 16 : 8;
   const size_t szF = c->elt;
   const int ch_cap = static_cast<int>(32768 / szF);
@@ -271,7 +281,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.perm = c->d_perm;
       a.buf[BUF_X] = X;
       a.buf[BUF_Y] = Y;
-      a.buf[BUF_ARENA] = c->d_arena;
+      a.buf[BUF_ARENA] = ar;
       a.first = 0;
       a.direct = 1;
       a.R = R;
@@ -323,6 +333,18 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     const int md = std::max(1, l.max_dst);
     const bool adj = adjoint && !l.force_fwd;
     const int mxp = std::max({1, l.max_dst, l.max_src});
+    if (c->mfma && c->dtype == HBF_C64 && !vec_c128 && R >= c->mfma_min_r) {
+      a.rc = R;
+      a.nchunks = 1;
+      a.acc = l.out_leaf;
+      a.alpha_re = alpha_re;
+      a.alpha_im = alpha_im;
+      a.src_cap = 0;
+      a.ch = 0;
+      const hipError_t e = launch_stage_mfma_c64(a, l.count, adj, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     const int pmr = sweep ? c->sweep_pipe_max_r : c->pipe_max_r;
     const bool rc1 = sweep && c->sweep_rc1 && R > pmr;
     if ((R <= pmr || rc1) && mxp <= 256) {
@@ -340,21 +362,6 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       if (c->dtype == HBF_C128) e = launch_pipe_c128(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
       else if (vec_c128) e = launch_pipe_c64_hi(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
       else e = launch_pipe_c64(a, l.count, a.nchunks, adj, c->r1_max_blocks, s);
-      if (e != hipSuccess) return e;
-      continue;
-    }
-    if (R == 1 && c->r1_kernel && l.max_src <= 255 && l.max_dst <= 256) {
-      a.rc = 1;
-      a.nchunks = 1;
-      a.acc = l.out_leaf;
-      a.alpha_re = alpha_re;
-      a.alpha_im = alpha_im;
-      a.src_cap = 0;
-      a.ch = 0;
-      hipError_t e;
-      if (c->dtype == HBF_C128) e = launch_stage_r1_c128(a, l.count, adj, c->r1_max_blocks, s);
-      else if (vec_c128) e = launch_stage_r1_c64_hi(a, l.count, adj, c->r1_max_blocks, s);
-      else e = launch_stage_r1_c64(a, l.count, adj, c->r1_max_blocks, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -400,18 +407,19 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
   return hipSuccess;
 }
 
-hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s) {
+hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s,
+                           void* arena) {
   hipError_t e;
   const std::vector<Launch>& fw = c->mv_direct ? c->mv_fwd : c->P.mv_fwd;
   const std::vector<Launch>& bw = c->mv_direct ? c->mv_adj : c->P.mv_adj;
-  if (!adjoint) e = run_launches(c, fw, false, xin, yout, R, vec_c128, 1.0, 0.0, s);
-  else e = run_launches(c, bw, true, yout, xin, R, vec_c128, 1.0, 0.0, s);
+  if (!adjoint) e = run_launches(c, fw, false, xin, yout, R, vec_c128, 1.0, 0.0, s, false, arena);
+  else e = run_launches(c, bw, true, yout, xin, R, vec_c128, 1.0, 0.0, s, false, arena);
   if (e != hipSuccess) return fail(HBF_EHIP, std::string("matvec launch: ") + hipGetErrorString(e));
   return HBF_OK;
 }
 
 // The two sweeps of the preconditioner (input in d_u, output in zout).
-static hipError_t enqueue_sweeps(hbf_ctx* c, void* zout, int R, bool adjoint, hipStream_t s) {
+hipError_t enqueue_sweeps(hbf_ctx* c, void* zout, int R, bool adjoint, hipStream_t s) {
   const bool paper = c->prec == HBF_PREC_PAPER_TRI;
   const double are = paper ? c->P.scale.real() : 1.0, aim = paper ? c->P.scale.imag() : 0.0;
   const bool v128 = c->dtype == HBF_C128;
@@ -600,16 +608,17 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     dmalloc(&c->d_pz, vbytes, "vectors");
     dmalloc(&c->d_flag, 256, "flag");
     // solver workspace (inner Krylov basis in the context dtype, FP64 outer vectors)
-    dmalloc(&c->d_krylov, static_cast<size_t>(c->restart + 1) * N * R * c->elt, "krylov");
+    const int nkry = solver_krylov_vectors(c->restart);
+    dmalloc(&c->d_krylov, static_cast<size_t>(nkry) * N * R * c->elt, "krylov");
     dmalloc(&c->d_w, static_cast<size_t>(N) * R * c->elt, "krylov");
     dmalloc(&c->d_x64, 4 * vbytes, "solver vectors");
     c->red_len = static_cast<size_t>(2 * 34) * R * 1024;
     dmalloc(&c->d_red, c->red_len * sizeof(double), "reduction");
-    dmalloc(&c->d_small,
-            static_cast<size_t>(R) * (2 * (c->restart + 2) * (c->restart + 4) + 1200) * sizeof(double),
-            "hessenberg");
-    c->workspace_bytes = static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16 + 4 * vbytes +
-                         static_cast<size_t>(c->restart + 2) * N * R * c->elt + 4 * vbytes;
+    dmalloc(&c->d_small, solver_small_bytes(c->restart, static_cast<int>(R)), "solver state");
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&c->h_flags), 256, hipHostMallocDefault), "hipHostMalloc");
+    for (auto& e : c->ev_step) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    c->workspace_bytes = static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16 + 5 * vbytes +
+                         static_cast<size_t>(nkry + 1) * N * R * c->elt + 4 * vbytes;
     if (c->prec != HBF_PREC_NONE) superleaf_entries(c.get());
     factor_leaves(c.get(), s);
     // release the host copies of the factors
@@ -780,7 +789,6 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     }
     return HBF_OK;
   }
-  if (k == "r1_kernel") { c->r1_kernel = value != 0; free_graphs(c); return HBF_OK; }
   if (k == "prog_pipe") {
     (void)hipDeviceSynchronize();
     free_graphs(c);
@@ -795,6 +803,13 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
   if (k == "pipe_max_r") {
     if (value < 0 || value > 1024) return fail(HBF_EINVAL, "hbf_tune: pipe_max_r out of range");
     c->pipe_max_r = static_cast<int>(value);
+    free_graphs(c);
+    return HBF_OK;
+  }
+  if (k == "mfma") { c->mfma = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "mfma_min_r") {
+    if (value < 1 || value > 1 << 20) return fail(HBF_EINVAL, "hbf_tune: mfma_min_r out of range");
+    c->mfma_min_r = static_cast<int>(value);
     free_graphs(c);
     return HBF_OK;
   }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -22,7 +23,6 @@ struct hbf_ctx {
   int64_t n = 0;
   int elt = 8;                 // bytes per factor entry
   bool wave_units = true;      // one wave per group for one- or two-RHS launches
-  bool r1_kernel = false;      // register-streaming kernel for one-RHS launches (LDS atomics)
   bool prog_pipe = true;       // pipelined wave teams in the sweep programs
   bool lane_split = true;      // pipelined kernels: several lanes share one output of a small unit
   bool sweep_rc1 = false;      // sweep stage launches above pipe_max_r: pipelined kernel, one RHS per chunk
@@ -30,6 +30,8 @@ struct hbf_ctx {
   bool prog_lds = true;        // sweep programs keep their vectors in LDS where they fit
   bool mv_direct = true;       // matvec launches of single-unit groups run direct over unit copies
   int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
+  bool mfma = true;            // complex64 stage launches with nrhs >= mfma_min_r run on the matrix cores
+  int mfma_min_r = 8;
   int r1_max_blocks = 0;       // persistent grid size of the stage kernels (0: resident capacity)
 
   // device memory
@@ -50,6 +52,10 @@ struct hbf_ctx {
   void* d_pz = nullptr;        // preconditioner output of the captured graphs
   bool use_graphs = true;      // replay the preconditioner sweeps from captured HIP graphs
   std::map<std::pair<int, int>, hipGraphExec_t> pc_graphs;  // (nrhs, adjoint) -> graph
+  // solver step graphs: (kind 0 Arnoldi step / 1 TFQMR iteration, nrhs, adjoint, restart) -> graph
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> step_graphs;
+  int* h_flags = nullptr;      // pinned host copies of the "any RHS active" flag of the last two steps
+  hipEvent_t ev_step[2] = {nullptr, nullptr};
   hbf::cd* d_diag64 = nullptr; // FP64 diagonal leaf blocks (with z), column-major
   int* d_flag = nullptr;
   // solver workspace
@@ -57,7 +63,7 @@ struct hbf_ctx {
   void* d_w = nullptr;         // one work vector (inner dtype)
   void* d_x64 = nullptr;       // FP64 outer vectors: x, r, b, d (N x max_nrhs each)
   double* d_red = nullptr;     // reduction scratch
-  double* d_small = nullptr;   // Hessenberg / Givens state
+  double* d_small = nullptr;   // per-RHS Krylov state (solver_small_bytes)
   size_t red_len = 0;
 
   std::vector<hbf::cd> diag_noz;  // host FP64 leaf blocks without z (for set_impedance)
@@ -73,10 +79,22 @@ namespace hbf {
 // complex64 factors this selects FP64 accumulation).  sweep: the launches
 // belong to the preconditioner sweeps (their stage launches may run one RHS
 // per chunk in the pipelined kernel whatever the RHS count).
+// arena: skeleton-vector buffer of at least arena_rows x R x 16 bytes (NULL:
+// the context's own).
 hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, void* X, void* Y, int R,
-                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep = false);
+                        bool vec_c128, double alpha_re, double alpha_im, hipStream_t s, bool sweep = false,
+                        void* arena = nullptr);
 
-hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s);
+hbf_status matvec_internal(hbf_ctx* c, void* xin, void* yout, int R, bool vec_c128, bool adjoint, hipStream_t s,
+                           void* arena = nullptr);
+// The preconditioner sweeps on the context's work vectors: input in d_u
+// (overwritten), output z (context dtype, internal layout).  Launches only,
+// so the caller may capture them.
+hipError_t enqueue_sweeps(hbf_ctx* c, void* zout, int R, bool adjoint, hipStream_t s);
+// Device bytes of the solver's per-RHS state for restart m and R right-hand
+// sides, and the number of Krylov-region vectors a solve needs.
+size_t solver_small_bytes(int m, int R);
+int solver_krylov_vectors(int m);
 hbf_status precond_internal(hbf_ctx* c, const void* rin, void* zout, int R, bool adjoint, hipStream_t s);
 
 }  // namespace hbf

@@ -770,6 +770,7 @@ void fill_stats(const Plan& P, hbf_stats_t* s, int elt) {
   s->build_seconds = P.build_seconds;
   s->scale_re = P.scale.real();
   s->scale_im = P.scale.imag();
+  s->arena_rows = P.arena_rows;
 }
 
 hbf_status hbf_plan_stats(const hbf_plan* plan, hbf_stats_t* out) {

@@ -17,6 +17,7 @@ from ._capi import (HBF_C64, HBF_C128, HBF_PREC_BLOCK_LU, HBF_PREC_NONE, HBF_PRE
 
 PREC = {"block": HBF_PREC_BLOCK_LU, "paper": HBF_PREC_PAPER_TRI, "none": HBF_PREC_NONE}
 DTYPE = {"c64": HBF_C64, "c128": HBF_C128}
+METHOD = {"gmres": _capi.HBF_GMRES, "tfqmr": _capi.HBF_TFQMR}
 
 
 def _curve_struct(curves):
@@ -161,7 +162,7 @@ class Context:
                                                    _stream_ptr(_torch(), self.device)))
         return z.reshape(r.shape)
 
-    def _solve(self, fn, b, tol, restart, max_iters, max_refine, mixed, x0, inner_tol):
+    def _solve(self, fn, b, tol, restart, max_iters, max_refine, mixed, x0, inner_tol, method):
         torch = _torch()
         io = "c64" if b.dtype == torch.complex64 else "c128"
         bb = self._prep(b, io)
@@ -170,7 +171,8 @@ class Context:
         else:
             x = torch.empty_like(bb)
         nr = bb.shape[0]
-        o = _capi.SolveOpts(tol, restart, max_iters, max_refine, int(mixed), int(x0 is not None), inner_tol)
+        o = _capi.SolveOpts(tol, restart, max_iters, max_refine, int(mixed), int(x0 is not None), inner_tol,
+                            METHOD[method])
         info = (_capi.SolveInfo * nr)()
         st = fn(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), nr, DTYPE[io], C.byref(o), info,
                 _stream_ptr(torch, self.device))
@@ -179,15 +181,32 @@ class Context:
                  for i in info]
         return x.reshape(b.shape), infos, st
 
-    def solve(self, b, tol=1e-6, restart=0, max_iters=0, max_refine=0, mixed=None, x0=None, inner_tol=0.0):
+    def solve(self, b, tol=1e-6, restart=0, max_iters=0, max_refine=0, mixed=None, x0=None, inner_tol=0.0,
+              method="gmres"):
         if mixed is None:
             mixed = self.dtype == "c64"
-        return self._solve(self.lib.hbf_solve, b, tol, restart, max_iters, max_refine, mixed, x0, inner_tol)
+        return self._solve(self.lib.hbf_solve, b, tol, restart, max_iters, max_refine, mixed, x0, inner_tol, method)
 
-    def solve_adjoint(self, g, tol=1e-6, restart=0, max_iters=0, max_refine=0, mixed=None, x0=None, inner_tol=0.0):
+    def solve_adjoint(self, g, tol=1e-6, restart=0, max_iters=0, max_refine=0, mixed=None, x0=None, inner_tol=0.0,
+                      method="gmres"):
         if mixed is None:
             mixed = self.dtype == "c64"
-        return self._solve(self.lib.hbf_solve_adjoint, g, tol, restart, max_iters, max_refine, mixed, x0, inner_tol)
+        return self._solve(self.lib.hbf_solve_adjoint, g, tol, restart, max_iters, max_refine, mixed, x0, inner_tol,
+                           method)
+
+    def impedance_grad(self, lam, x):
+        """-sum over right-hand sides of lam * conj(x) (hbf_impedance_grad), shape (N,)."""
+        torch = _torch()
+        io = "c64" if x.dtype == torch.complex64 else "c128"
+        ll = self._prep(lam, io)
+        xx = self._prep(x, io)
+        if ll.shape != xx.shape:
+            raise ValueError("lam and x must have the same shape")
+        g = torch.empty(self.n, dtype=xx.dtype, device=self.device)
+        check(self.lib, self.lib.hbf_impedance_grad(self.h, C.c_void_p(ll.data_ptr()), C.c_void_p(xx.data_ptr()),
+                                                    xx.shape[0], DTYPE[io], C.c_void_p(g.data_ptr()),
+                                                    _stream_ptr(torch, self.device)))
+        return g
 
     def tune(self, key, value):
         check(self.lib, self.lib.hbf_tune(self.h, key.encode(), int(value)))
