@@ -47,18 +47,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the sources that decide what the single-RHS matvec reads and writes: the
+# factor layout, the launch schedule and the stage kernel
+MATVEC_SOURCES = ("hbf_internal.h", "kernels.h", "plan.cpp", "ctx.cpp", "stage_pipe.hip")
+
+
 def sources_digest():
-    """sha256 over the library's sources (name and contents, in name order):
-    identifies the build a set of hardware-counter readings was taken on."""
+    """sha256 over the single-RHS matvec's sources (name and contents, in
+    name order): identifies the build a set of hardware-counter readings was
+    taken on."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1901_11371_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        path = os.path.join(d, name)
-        if os.path.isfile(path):
-            h.update(name.encode())
-            with open(path, "rb") as f:
-                h.update(f.read())
+    for name in sorted(MATVEC_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
@@ -89,10 +93,17 @@ def main():
     ap.add_argument("--no-srhs", action="store_true", help="skip the semicircle seconds-per-RHS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch", "matvec_batch"],
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch", "matvec_batch", "scale", "iterations"],
                     help="matvec / precond: only the single-RHS apply loop; precond_batch: the nrhs-RHS "
                          "preconditioner loop with the autotuned parameters (for profiling)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--srhs-geometry", default="semicircle", choices=["semicircle", "spiral"],
+                    help="geometry of the seconds-per-RHS comparison")
+    ap.add_argument("--srhs-n", type=int, default=0, help="N of the seconds-per-RHS comparison (0: --n)")
+    ap.add_argument("--method", default="gmres", choices=["gmres", "tfqmr"],
+                    help="Krylov method of the seconds-per-RHS and scale solves")
+    ap.add_argument("--superleaf", type=int, default=0,
+                    help="log2 leaves per exactly inverted diagonal block of the sweeps (0: library default)")
     ap.add_argument("--params", default=None,
                     help="JSON object of execution parameters to set instead of autotuning (profiling modes)")
     args = ap.parse_args()
@@ -108,13 +119,20 @@ def main():
     from paper_1901_11371_amd.hbf import Context
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.mode == "scale":
+        scale_workload(args)
+        return
+    if args.mode == "iterations":
+        iteration_counts(args)
+        return
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
     n, R, m = args.n, args.nrhs, args.restart
     wl = inputs.workload(2, n=n, nrhs=R)
     log(f"[bench] building spiral N={n} (host construction + upload)")
     t0 = time.time()
-    ctx = Context(wl.curves, inputs.KAPPA, wl.n0, wl.tol, dtype="c64", max_nrhs=R, restart=m)
+    ctx = Context(wl.curves, inputs.KAPPA, wl.n0, wl.tol, dtype="c64", max_nrhs=R, restart=m,
+                  superleaf=args.superleaf)
     t_build = time.time() - t0
     st = ctx.stats
     log(f"[bench] built in {t_build:.1f}s: mean rank {st['mean_rank']:.2f} max {st['max_rank']} "
@@ -222,7 +240,7 @@ def main():
 
     srhs = None
     if not args.no_srhs:
-        srhs = seconds_per_rhs(n, R, m)
+        srhs = seconds_per_rhs(args.srhs_geometry, args.srhs_n or n, R, m, args.method)
 
     cpu = None
     if not args.no_cpu:
@@ -268,25 +286,27 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def seconds_per_rhs(n, R, m):
-    """Semicircle at N: a batched complex64 solve of R plane waves vs the plain
-    single-RHS complex128 solve, both to relres <= 1e-6."""
-    import numpy as np
+def seconds_per_rhs(geometry, n, R, m, method):
+    """A batched complex64 solve of R plane waves vs the plain single-RHS
+    complex128 solve on the same geometry, both to relres <= 1e-6."""
     import torch
 
     from paper_1901_11371_amd import inputs
     from paper_1901_11371_amd.hbf import Context
     dev = torch.device("cuda", 0)
-    curves = inputs.semicircle(n)
+    curves = inputs.semicircle(n) if geometry == "semicircle" else inputs.archimedean_spiral(n)
     angles = inputs.uniform_angles(R)
     B = torch.tensor(inputs.plane_wave_rhs(curves, angles), dtype=torch.complex128, device=dev)
+    max_iters = 500 if geometry == "semicircle" else 20000
     t0 = time.time()
     ctx = Context(curves, inputs.KAPPA, 64, 1e-6, dtype="c64", max_nrhs=R, restart=m, cache_plan=True)
-    log(f"[bench] semicircle N={n} complex64 context built in {time.time()-t0:.1f}s")
-    ctx.solve(B, tol=1e-6)
+    log(f"[bench] {geometry} N={n} complex64 context built in {time.time()-t0:.1f}s")
+    kw = dict(tol=1e-6, max_iters=max_iters, method=method)
+    if geometry == "semicircle":
+        ctx.solve(B, **kw)   # warm-up (graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    X, infos, _ = ctx.solve(B, tol=1e-6)
+    X, infos, _ = ctx.solve(B, **kw)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     x0 = X[0].clone()
@@ -295,26 +315,164 @@ def seconds_per_rhs(n, R, m):
     torch.cuda.empty_cache()
     t0 = time.time()
     ctx128 = Context(curves, inputs.KAPPA, 64, 1e-6, dtype="c128", max_nrhs=1, restart=m, cache_plan=True)
-    log(f"[bench] semicircle complex128 context built in {time.time()-t0:.1f}s (host plan reused)")
+    log(f"[bench] {geometry} complex128 context built in {time.time()-t0:.1f}s (host plan reused)")
     b0 = B[0].contiguous()
-    ctx128.solve(b0, tol=1e-6)
+    if geometry == "semicircle":
+        ctx128.solve(b0, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x128, info128, _ = ctx128.solve(b0, tol=1e-6)
+    x128, info128, _ = ctx128.solve(b0, **kw)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     ctx128.close()
     diff = float(torch.linalg.norm(x0 - x128) / torch.linalg.norm(x128))
-    out = {"workload": f"semicircle N={n}, {R} plane waves, relres 1e-6",
+    out = {"workload": f"{geometry} N={n}, {R} plane waves, relres 1e-6, {method}",
            "batched_c64": t_batched / R, "plain_c128": t_plain,
            "speedup": t_plain / (t_batched / R),
            "batched_iters_max": max(i["iters"] for i in infos),
            "batched_relres_max": max(i["relres"] for i in infos),
+           "batched_converged": all(i["converged"] for i in infos),
            "plain_iters": info128[0]["iters"], "plain_relres": info128[0]["relres"],
+           "plain_converged": info128[0]["converged"],
            "batched_c64_vs_c128_solution_rel_diff": diff}
-    log(f"[bench] s/RHS semicircle: batched c64 {t_batched/R*1e3:.2f} ms, plain c128 {t_plain*1e3:.1f} ms, "
-        f"solution diff {diff:.2e}")
+    log(f"[bench] s/RHS {geometry}: batched c64 {t_batched/R*1e3:.2f} ms, plain c128 {t_plain*1e3:.1f} ms, "
+        f"iterations {out['batched_iters_max']} / {out['plain_iters']}, solution diff {diff:.2e}")
     return out
+
+
+def scale_workload(args):
+    """The scale workload: 8 disjoint strips and arcs (random lengths and
+    orientations), N = 2^22, 256 plane waves solved in chunks of 64 with
+    complex64 factors and FP64 refinement to relres 1e-6; matvec parity on
+    sampled exact rows first."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from oracle import efie
+    from paper_1901_11371_amd import inputs
+    from paper_1901_11371_amd.hbf import Context
+    n = args.n if args.n != (1 << 20) else (1 << 22)
+    nrhs_total, chunk = 256, 64
+    wl = inputs.workload(4, n=n, nrhs=nrhs_total)
+    dev = torch.device("cuda", 0)
+    log(f"[scale] building {wl.curves.ncurves} curves N={n} (host construction + upload)")
+    t0 = time.time()
+    ctx = Context(wl.curves, inputs.KAPPA, wl.n0, wl.tol, dtype="c64", max_nrhs=chunk, restart=args.restart)
+    t_build = time.time() - t0
+    st = ctx.stats
+    log(f"[scale] built in {t_build:.1f}s: mean rank {st['mean_rank']:.2f} max {st['max_rank']} "
+        f"butterfly {st['bytes_butterfly']/1e9:.2f} GB dense {st['bytes_dense']/1e9:.2f} GB "
+        f"leaf inverses {st['bytes_precond']/1e9:.2f} GB workspace {st['bytes_workspace']/1e9:.2f} GB")
+    # matvec parity on sampled rows (oracle, one process per core)
+    rho, w = efie.segments(wl.curves.xy, wl.curves.node_off)
+    cores = os.cpu_count() or 1
+    rows = np.sort(np.random.default_rng(inputs.SEED_BASE + 4).choice(n, 2 * cores, replace=False))
+    X = inputs.random_complex((2, n), 54)
+    Y = ctx.matvec(torch.tensor(X, dtype=torch.complex64, device=dev)).cpu().numpy()
+    t0 = time.perf_counter()
+    parts = np.array_split(rows, cores)
+    with mp.get_context("spawn").Pool(cores) as pool:
+        outs = pool.map(_oracle_rows, [(p, X.T, rho, w, inputs.KAPPA) for p in parts])
+    ref = np.concatenate(outs).T
+    err = float(np.linalg.norm(Y[:, rows] - ref) / np.linalg.norm(ref))
+    log(f"[scale] matvec sampled rel err {err:.3e} ({len(rows)} rows, oracle {time.perf_counter()-t0:.1f}s)")
+    # apply timings
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+    x1 = torch.tensor(X[0], dtype=torch.complex64, device=dev)
+    t_mv1 = timed(lambda: ctx.matvec(x1), 5)
+    XB = torch.tensor(inputs.random_complex((chunk, n), 55), dtype=torch.complex64, device=dev)
+    t_mvb = timed(lambda: ctx.matvec(XB), 2)
+    t_pcb = timed(lambda: ctx.precond(XB), 1)
+    del XB
+    log(f"[scale] matvec 1 RHS {t_mv1*1e3:.2f} ms, {chunk} RHS {t_mvb*1e3:.1f} ms; preconditioner {chunk} RHS "
+        f"{t_pcb*1e3:.1f} ms")
+    # 256 RHS in chunks of 64
+    infos = []
+    t_solve = 0.0
+    for c0 in range(0, nrhs_total, chunk):
+        B = torch.tensor(inputs.plane_wave_rhs(wl.curves, wl.angles[c0:c0 + chunk]), dtype=torch.complex128,
+                         device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, status = ctx.solve(B, tol=1e-6, max_iters=2000, method=args.method)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_solve += dt
+        infos += info
+        log(f"[scale] RHS {c0}..{c0 + chunk - 1}: {dt:.1f}s, iters max {max(i['iters'] for i in info)}, "
+            f"relres max {max(i['relres'] for i in info):.2e}, status {status}")
+        del B
+    ctx.close()
+    out = {"mode": "scale", "workload": f"{wl.curves.ncurves} strips/arcs N={n}, {nrhs_total} plane waves in "
+                                        f"chunks of {chunk}, complex64 factors, relres 1e-6, {args.method}",
+           "n": n, "build_s": t_build, "matvec_sampled_rel_err": err, "sampled_rows": len(rows),
+           "matvec_1rhs_ms": t_mv1 * 1e3, f"matvec_{chunk}rhs_ms": t_mvb * 1e3,
+           f"precond_{chunk}rhs_ms": t_pcb * 1e3,
+           "solve_s_per_rhs": t_solve / nrhs_total, "iters_max": max(i["iters"] for i in infos),
+           "relres_max": max(i["relres"] for i in infos), "converged": all(i["converged"] for i in infos),
+           "bytes_butterfly": st["bytes_butterfly"], "bytes_dense": st["bytes_dense"],
+           "bytes_precond": st["bytes_precond"], "mean_rank": st["mean_rank"], "max_rank": st["max_rank"]}
+    print(json.dumps(out), flush=True)
+
+
+def iteration_counts(args):
+    """Iteration counts with and without the preconditioner over the
+    families of the paper's iteration study (Sec. 4): N (semicircle), arc
+    angle, Archimedean-spiral rotation and arc-array size; one plane wave at
+    pi/6, complex128 factors and vectors, relres 1e-6."""
+    import math
+
+    import torch
+
+    from paper_1901_11371_amd import inputs
+    from paper_1901_11371_amd.hbf import Context
+    dev = torch.device("cuda", 0)
+    n = 1 << 14
+    method = args.method
+    cap = 3000
+    fams = {
+        "N (semicircle)": [(f"N={k}", inputs.semicircle(k)) for k in (1 << 12, 1 << 13, 1 << 14, 1 << 15, 1 << 16)],
+        "arc angle": [(f"angle={a / math.pi:.2f}pi", inputs.arc_with_angle(n, a))
+                      for a in (math.pi / 4, math.pi / 2, math.pi, 1.5 * math.pi, 1.9 * math.pi)],
+        "spiral rotation": [(f"rotation={r / math.pi:.0f}pi", inputs.archimedean_spiral(n, math.pi, math.pi + r))
+                            for r in (math.pi, 2 * math.pi, 3 * math.pi, 4 * math.pi, 5 * math.pi)],
+        "arc array": [(f"count={k}", inputs.arc_array(n, k)) for k in (1, 2, 4, 8, 16)],
+    }
+    out = {"mode": "iterations", "method": method, "tol": 1e-6, "cap": cap, "families": {}}
+    for fam, members in fams.items():
+        rows = []
+        for label, c in members:
+            b = torch.tensor(inputs.plane_wave_rhs(c, [math.pi / 6])[0], device=dev)
+            row = {"member": label, "n": c.n_segments}
+            for prec in ("block", "none"):
+                ctx = Context(c, inputs.KAPPA, 64, 1e-6, dtype="c128", prec=prec, max_nrhs=1, restart=100)
+                t0 = time.perf_counter()
+                _, info, st = ctx.solve(b, tol=1e-6, restart=100, max_iters=cap, method=method)
+                torch.cuda.synchronize()
+                row[f"iters_{prec}"] = info[0]["iters"]
+                row[f"converged_{prec}"] = bool(info[0]["converged"])
+                row[f"seconds_{prec}"] = time.perf_counter() - t0
+                ctx.close()
+            log(f"[iterations] {fam} {label}: with the preconditioner {row['iters_block']}"
+                f"{'' if row['converged_block'] else '+'} , without {row['iters_none']}"
+                f"{'' if row['converged_none'] else '+'}")
+            rows.append(row)
+        out["families"][fam] = rows
+    print(json.dumps(out), flush=True)
 
 
 def _oracle_rows(args):

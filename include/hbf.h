@@ -83,6 +83,8 @@ typedef struct {
   int32_t cache_plan; /* 1: keep this host factorisation in a one-entry process cache, so a later
                          build of the same curve/kappa/leaf/tol/preconditioner (any dtype) skips
                          the host construction; 0: no caching (a cache hit is still used) */
+  int32_t superleaf;  /* leaf solves of the sweeps invert diagonal blocks of 2^superleaf leaves
+                         exactly (2 or 3; <= 0 selects 2) */
 } hbf_build_opts;
 
 /* Krylov method of the inner solves. */
@@ -208,7 +210,9 @@ hbf_status hbf_impedance_grad(hbf_ctx* ctx, const void* lam, const void* x, int3
  *                   from HIP graphs,
  *   "mfma"          1 = complex64 stage launches with nrhs >= mfma_min_r run
  *                   as complex GEMMs on the FP32 matrix cores (default 1),
- *   "mfma_min_r"    smallest nrhs for the matrix-core stage launches (default 8).
+ *   "mfma_min_r"    smallest nrhs for the matrix-core stage launches (default 8),
+ *   "mfma_tiles"    right-hand sides per wave of those launches, in 16-column
+ *                   tiles: 1, 2 or 4 (default 4).
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);
 

@@ -8,7 +8,9 @@ fastest:
 * ``prog_levels``: subtrees of at most 2^p leaves are swept inside one
   workgroup program (deep subtrees: fewer launches and cheap step
   barriers, but one workgroup per RHS chunk streams their factors);
-* the stage kernel of the matvec and, separately, of the big sweep blocks:
+* the stage kernel of the matvec and, separately, of the big sweep blocks
+  (with complex64 factors and 8 or more RHS also the matrix-core kernel at
+  16, 32 or 64 RHS per wave):
   the software-pipelined wave teams (``pipe_max_r`` / ``sweep_pipe_max_r``
   >= nrhs), or one unit per wave / workgroup (``wave_units``); and whether
   the sweeps' stage launches use the pipelined kernel with one RHS per chunk
@@ -27,12 +29,21 @@ import torch
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "autotune.json")
 
 # stage-kernel variants: name -> hbf_tune settings
+_VALU = {"mfma": 0, "mfma_min_r": 8, "mfma_tiles": 4}
+_NO_PIPE = {"pipe_max_r": 4, "sweep_pipe_max_r": 4, "wave_units": 1, "sweep_rc1": 0}
 KERNELS = {
-    "pipe": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0},
-    "wave": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0},
-    "wave+sweep_pipe": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0},
-    "pipe+sweep_wave": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0},
-    "wave+rc1": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 1},
+    "pipe": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0,
+                       **_VALU},
+    "wave": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0, **_VALU},
+    "wave+sweep_pipe": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0,
+                                  **_VALU},
+    "pipe+sweep_wave": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0,
+                                  **_VALU},
+    "wave+rc1": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 1, **_VALU},
+    # matrix-core stage launches with 16, 32 or 64 right-hand sides per wave (complex64 only)
+    "mfma16": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 1},
+    "mfma32": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 2},
+    "mfma64": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 4},
 }
 
 
@@ -97,6 +108,8 @@ def autotune(ctx, nrhs=1, reps=2, prog_levels=(4, 5, 6, 7, 8), kernels=tuple(KER
         ctx.tune("prog_levels", p)
     res = {}
     for name in kernels:
+        if name.startswith("mfma") and (ctx.dtype != "c64" or nrhs < 8):
+            continue
         for k, v in KERNELS[name](nrhs).items():
             ctx.tune(k, v)
         t = _time(lambda: ctx.matvec(x), reps)

@@ -222,6 +222,8 @@ uint64_t plan_key(const hbf_curve* curve, double kappa, int leaf, double tol, co
   mix(&prec, sizeof(prec));
   const double eta0 = opts ? opts->eta0 : 0.0;
   mix(&eta0, sizeof(eta0));
+  const int sl = opts ? opts->superleaf : 0;
+  mix(&sl, sizeof(sl));
   if (opts && opts->z) {
     const int64_t n = curve->node_off[curve->ncurves] - curve->ncurves;
     mix(opts->z, sizeof(double) * 2 * n);
@@ -341,7 +343,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       a.src_cap = 0;
       a.ch = 0;
-      const hipError_t e = launch_stage_mfma_c64(a, l.count, adj, s);
+      const hipError_t e = launch_stage_mfma_c64(a, l.count, c->mfma_tiles, adj, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -807,6 +809,12 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     return HBF_OK;
   }
   if (k == "mfma") { c->mfma = value != 0; free_graphs(c); return HBF_OK; }
+  if (k == "mfma_tiles") {
+    if (value != 1 && value != 2 && value != 4) return fail(HBF_EINVAL, "hbf_tune: mfma_tiles must be 1, 2 or 4");
+    c->mfma_tiles = static_cast<int>(value);
+    free_graphs(c);
+    return HBF_OK;
+  }
   if (k == "mfma_min_r") {
     if (value < 1 || value > 1 << 20) return fail(HBF_EINVAL, "hbf_tune: mfma_min_r out of range");
     c->mfma_min_r = static_cast<int>(value);

@@ -66,7 +66,8 @@ hipError_t launch_prog_pipe_c128(const StageArgs& a, const int32_t* steps, int s
                                  hipStream_t s);
 // Many right-hand sides with complex64 factors and vectors: one wave per group,
 // complex GEMMs on FP32 matrix cores (stage_mfma.hip).
-hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, bool adjoint, hipStream_t s);
+// tiles: 16-RHS column tiles per wave (1, 2 or 4)
+hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, bool adjoint, hipStream_t s);
 // Wave-per-group variant (4 groups per workgroup, wave_lds bytes of LDS each).
 hipError_t launch_stage_wave_c64(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
 hipError_t launch_stage_wave_c128(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);

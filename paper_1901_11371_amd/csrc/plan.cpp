@@ -701,7 +701,9 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
   // Matrices live in a region after the factors and are filled by the leaf
   // factorisation.
   const hbf_prec prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
-  P.sl = std::min(2, P.V);
+  const int sl_req = (opts && opts->superleaf > 0) ? opts->superleaf : 2;
+  if (sl_req < 2 || sl_req > 3) throw std::invalid_argument("hbf_build: superleaf must be 2 or 3");
+  P.sl = std::min(sl_req, P.V);
   P.sl_slab = (leaf % 8 == 0) ? 8 : leaf;
   const int s_leaves = 1 << P.sl;
   const int slabs = leaf / P.sl_slab;

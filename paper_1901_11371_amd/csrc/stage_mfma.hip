@@ -14,8 +14,9 @@
 // The adjoint uses M^H.  The complex product is four real products on
 // v_mfma_f32_16x16x4_f32 (re*re - im*im, re*im + im*re) with FP32
 // accumulation: one wave takes one group of units (units writing the same
-// rows, summed in the accumulators) for up to 64 right-hand sides (four
-// 16-column tiles), one 16-row output tile at a time, 4 source rows per step.
+// rows, summed in the accumulators) for NT 16-column tiles of right-hand
+// sides (NT = 1, 2 or 4: 16, 32 or 64 RHS per wave, an execution parameter),
+// one 16-row output tile at a time, 4 source rows per step.
 #include "kernels.h"
 
 namespace hbf {
@@ -25,7 +26,6 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWaves = 4;  // waves (groups) per workgroup
-constexpr int kNT = 4;         // 16-column RHS tiles per wave (64 RHS)
 
 struct UnitView {
   int64_t mat, perm;
@@ -90,7 +90,7 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <bool ADJ>
+template <bool ADJ, int kNT>
 __global__ void __launch_bounds__(64 * kMfmaWaves) k_stage_mfma(StageArgs a, int ngroups, int nrchunks) {
   __shared__ uint8_t s_inv[kMfmaWaves][512];
   const int wave = threadIdx.x >> 6;
@@ -207,18 +207,25 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_stage_mfma(StageArgs a, int
   }
 }
 
-}  // namespace
-
-hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, bool adjoint, hipStream_t s) {
-  const int nrchunks = (a.R + 16 * kNT - 1) / (16 * kNT);
+template <int NT>
+hipError_t launch_nt(const StageArgs& a, int ngroups, bool adjoint, hipStream_t s) {
+  const int nrchunks = (a.R + 16 * NT - 1) / (16 * NT);
   const int64_t waves = static_cast<int64_t>(ngroups) * nrchunks;
   const unsigned blocks = static_cast<unsigned>((waves + kMfmaWaves - 1) / kMfmaWaves);
   if (blocks == 0) return hipSuccess;
   if (adjoint)
-    hipLaunchKernelGGL(k_stage_mfma<true>, dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks);
+    hipLaunchKernelGGL((k_stage_mfma<true, NT>), dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks);
   else
-    hipLaunchKernelGGL(k_stage_mfma<false>, dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks);
+    hipLaunchKernelGGL((k_stage_mfma<false, NT>), dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, bool adjoint, hipStream_t s) {
+  if (tiles >= 4) return launch_nt<4>(a, ngroups, adjoint, s);
+  if (tiles == 2) return launch_nt<2>(a, ngroups, adjoint, s);
+  return launch_nt<1>(a, ngroups, adjoint, s);
 }
 
 }  // namespace hbf

@@ -29,14 +29,15 @@ def _curve_struct(curves):
 
 
 def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, nthreads=0, eta0=0.0,
-          cache_plan=0):
+          cache_plan=0, superleaf=0):
     keep = []
     zp = None
     if z is not None:
         zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
         keep.append(zz)
         zp = zz.ctypes.data_as(C.POINTER(C.c_double))
-    o = _capi.BuildOpts(DTYPE[dtype], PREC[prec], eta0, zp, max_nrhs, restart, device, nthreads, cache_plan)
+    o = _capi.BuildOpts(DTYPE[dtype], PREC[prec], eta0, zp, max_nrhs, restart, device, nthreads, cache_plan,
+                        superleaf)
     return o, keep
 
 
@@ -53,14 +54,15 @@ class HostPlan:
     """Host-side factorisation evaluated in FP64 on the CPU (construction
     checks; not a compute path of the library)."""
 
-    def __init__(self, curves, kappa, leaf, tol, prec="block", z=None, nthreads=0, lib=None, dtype="c128"):
+    def __init__(self, curves, kappa, leaf, tol, prec="block", z=None, nthreads=0, lib=None, dtype="c128",
+                 superleaf=0):
         # dtype: the device storage type whose sweep schedule the plan mirrors
         # (it sets which sweep programs keep their vectors in LDS); the host
         # evaluation is FP64 either way
         self.lib = lib or _capi.load()
         cs, keep = _curve_struct(curves)
         self._keep = list(keep)
-        o, k2 = _opts(dtype, prec, z, nthreads=nthreads)
+        o, k2 = _opts(dtype, prec, z, nthreads=nthreads, superleaf=superleaf)
         self._keep += k2
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_plan_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))
@@ -113,7 +115,7 @@ class Context:
     device, shape (N,) or (nrhs, N), complex64 or complex128."""
 
     def __init__(self, curves, kappa, leaf, tol, dtype="c64", prec="block", z=None, max_nrhs=1, restart=30,
-                 device=0, nthreads=0, cache_plan=False):
+                 device=0, nthreads=0, cache_plan=False, superleaf=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("hbf.Context needs a HIP device")
@@ -121,7 +123,7 @@ class Context:
         self.device = torch.device("cuda", device)
         cs, keep = _curve_struct(curves)
         o, k2 = _opts(dtype, prec, z, max_nrhs=max_nrhs, restart=restart, device=device, nthreads=nthreads,
-                      cache_plan=int(cache_plan))
+                      cache_plan=int(cache_plan), superleaf=superleaf)
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))
         del keep, k2

@@ -154,6 +154,42 @@ def archimedean_spiral(n: int, theta0: float = math.pi, theta1: float = 6 * math
     return _single(xy, "spiral", a=a)
 
 
+def arc_with_angle(n: int, angle: float) -> Curves:
+    """Circular arc of arc length n/10 subtending `angle` (radius = length /
+    angle), symmetric about the y axis; the family of the paper's
+    arc-angle study (Sec. 4)."""
+    length = n / SEGMENTS_PER_WAVELENGTH
+    radius = length / angle
+    c = circular_arc(n, radius, math.pi / 2 - angle / 2, math.pi / 2 + angle / 2)
+    c.name = "arc"
+    c.meta["angle"] = angle
+    return c
+
+
+def arc_array(n_total: int, count: int, angle: float = math.pi / 2, gap: float = 2.0) -> Curves:
+    """`count` identical circular arcs (each subtending `angle`, n_total /
+    count segments) side by side along the x axis, `gap` wavelengths between
+    the end of one and the start of the next; the family of the paper's
+    arc-array study (Sec. 4).  Curves are concatenated left to right."""
+    n = n_total // count
+    if n * count != n_total:
+        raise ValueError("n_total must be a multiple of count")
+    length = n / SEGMENTS_PER_WAVELENGTH
+    radius = length / angle
+    chord = 2 * radius * math.sin(angle / 2)
+    pieces = []
+    for k in range(count):
+        cx = k * (chord + gap)
+        # arc above its chord, endpoints at x = cx - chord/2 and cx + chord/2
+        cy = -radius * math.cos(angle / 2)
+        pieces.append(circular_arc(n, radius, math.pi / 2 + angle / 2, math.pi / 2 - angle / 2,
+                                   center=(cx, cy)).xy)
+    node_off = np.zeros(count + 1, dtype=np.int64)
+    node_off[1:] = np.cumsum([p.shape[0] for p in pieces])
+    return Curves(np.ascontiguousarray(np.concatenate(pieces, axis=0)), node_off, "arc_array",
+                  dict(count=count, angle=angle, gap=gap))
+
+
 def multi_curve(n_total: int, ncurves: int = 8, seed: int | None = None) -> Curves:
     """Disjoint strips (even index) and circular arcs (odd index) of random
     length and orientation, centred on a 4 x 2 grid; segment counts are

@@ -148,6 +148,8 @@ TUNINGS = [
     {"mfma_min_r": 1, "mv_direct": 0},
     {"mfma_min_r": 1, "prog_levels": 0},
     {"mfma_min_r": 1, "prog_levels": 3, "use_graphs": 0},
+    {"mfma_min_r": 1, "mfma_tiles": 1},
+    {"mfma_min_r": 1, "mfma_tiles": 2, "mv_direct": 0},
 ]
 
 
@@ -191,16 +193,17 @@ def test_execution_parameters_keep_results(torch, spiral, tuning_refs, tuning):
     ctx.close()
 
 
-@pytest.mark.parametrize("mfma", [1, 0])
-def test_64_rhs_on_matrix_cores(torch, spiral, mfma):
+@pytest.mark.parametrize("mfma,tiles", [(1, 4), (1, 2), (1, 1), (0, 4)])
+def test_64_rhs_on_matrix_cores(torch, spiral, mfma, tiles):
     """64 right-hand sides (the batched launch shape): matvec and
     preconditioner, forward and adjoint, with the matrix-core stage launches
     (and without them), against the oracle, with relative L2 and worst-row
     bars, and each batch column against the single-RHS product."""
     c, A = spiral
-    _say(f"[64 rhs] spiral 4096 c64 mfma={mfma}")
+    _say(f"[64 rhs] spiral 4096 c64 mfma={mfma} tiles={tiles}")
     ctx = _ctx(c, "c64", max_nrhs=64)
     ctx.tune("mfma", mfma)
+    ctx.tune("mfma_tiles", tiles)
     X = inputs.random_complex((64, 4096), 37)
     Xt = torch.tensor(X, dtype=torch.complex64, device="cuda")
     for adj in (False, True):
@@ -215,6 +218,30 @@ def test_64_rhs_on_matrix_cores(torch, spiral, mfma):
         errz, rowz = _rel(Z, refz), _rowmax(Z, refz)
         _say(f"  precond (16 rhs) adjoint={adj} rel err {errz:.3e} worst row {rowz:.3e}")
         assert errz < 5e-5 and rowz < 2e-4
+    ctx.close()
+
+
+@pytest.mark.parametrize("superleaf", [3])
+@pytest.mark.parametrize("prec", ["block", "paper"])
+def test_superleaf_sizes(torch, spiral, prec, superleaf):
+    """The leaf solves of the sweeps invert diagonal blocks of 2^superleaf
+    leaves; the 8-leaf size gives the oracle's preconditioner as the default
+    4-leaf one does (1, 5 and 16 RHS, forward and adjoint)."""
+    from paper_1901_11371_amd.hbf import Context
+    c, A = spiral
+    _say(f"[superleaf] {superleaf} prec={prec}")
+    ctx = Context(c, KAPPA, 64, 1e-6, dtype="c64", prec=prec, max_nrhs=16, superleaf=superleaf)
+    X = inputs.random_complex((16, 4096), 38)
+    f = (lambda v, adj: efie.precond_block_apply(A, v, 64, adjoint=adj)) if prec == "block" else \
+        (lambda v, adj: efie.precond_paper_apply(A, v, adjoint=adj))
+    for adj in (False, True):
+        ref = f(X.T, adj).T
+        for nr in (1, 5, 16):
+            Xt = torch.tensor(X[:nr], dtype=torch.complex64, device="cuda")
+            Z = ctx.precond(Xt if nr > 1 else Xt[0], adjoint=adj).cpu().numpy().reshape(nr, -1)
+            err, rowerr = _rel(Z, ref[:nr]), _rowmax(Z, ref[:nr])
+            _say(f"  adjoint={adj} nrhs={nr} rel err {err:.3e} worst row {rowerr:.3e}")
+            assert err < 5e-5 and rowerr < 2e-4
     ctx.close()
 
 

@@ -1,0 +1,94 @@
+"""Preconditioner parity beyond the sizes a dense oracle test can reach.
+
+* N = 2^14 spiral: P^{-1} r and P^{-H} r against stored oracle values
+  (tests/golden/make_precond_2p14.py, dense FP64 definitions), both
+  readings, complex128 and complex64, one RHS and a batch of 16 (matrix-core
+  stage launches); at this size the sweeps run block levels above the
+  subtree programs.
+* N = 2^16 parabola: the device sweeps against the host FP64 executor of the
+  same factorisation and schedules (hbf_plan_precond, itself checked against
+  the dense oracle at N = 4096), forward and adjoint, 1 and 64 RHS.
+Relative L2 and worst-row bars."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1901_11371_amd import inputs
+
+pytestmark = pytest.mark.gpu
+KAPPA = 2 * math.pi
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _rowmax(a, b):
+    return float(np.abs(np.atleast_2d(a) - np.atleast_2d(b)).max() / np.abs(np.atleast_2d(b)).max())
+
+
+@pytest.fixture(scope="module")
+def golden14(golden_dir):
+    return dict(np.load(os.path.join(golden_dir, "precond_spiral_16384.npz")))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("prec", ["block", "paper"])
+def test_precond_spiral_2p14_vs_stored_oracle(torch, golden14, prec, dtype):
+    from paper_1901_11371_amd.hbf import Context
+    n = 1 << 14
+    c = inputs.archimedean_spiral(n)
+    _say(f"[precond 2^14] prec={prec} dtype={dtype}")
+    ctx = Context(c, KAPPA, 64, 1e-6, dtype=dtype, prec=prec, max_nrhs=16, cache_plan=True)
+    td = torch.complex64 if dtype == "c64" else torch.complex128
+    R = golden14["r"]
+    bar, rowbar = (2e-6, 1e-5) if dtype == "c128" else (5e-5, 2e-4)
+    for adj in (False, True):
+        ref = golden14[f"{prec}_{'adj' if adj else 'fwd'}"]
+        Z = np.stack([ctx.precond(torch.tensor(R[i], dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
+                      for i in range(R.shape[0])])
+        err, rowerr = _rel(Z, ref), _rowmax(Z, ref)
+        RB = np.tile(R, (8, 1))
+        ZB = ctx.precond(torch.tensor(RB, dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
+        errb, rowb = _rel(ZB, np.tile(ref, (8, 1))), _rowmax(ZB, np.tile(ref, (8, 1)))
+        _say(f"  adjoint={adj}: 1 RHS rel {err:.3e} row {rowerr:.3e}; 16 RHS rel {errb:.3e} row {rowb:.3e}")
+        assert err < bar and rowerr < rowbar
+        assert errb < bar and rowb < rowbar
+    ctx.close()
+
+
+def test_precond_parabola_2p16_vs_host_executor(torch):
+    from paper_1901_11371_amd.hbf import Context, HostPlan
+    n = 1 << 16
+    c = inputs.parabola(n)
+    _say("[precond 2^16] parabola c64, device sweeps vs host FP64 executor")
+    plan = HostPlan(c, KAPPA, 64, 1e-6, dtype="c64")
+    ctx = Context(c, KAPPA, 64, 1e-6, dtype="c64", max_nrhs=64)
+    X = inputs.random_complex((64, n), 91)
+    for adj in (False, True):
+        ref = plan.precond(X[:4], adjoint=adj)
+        z1 = np.stack([ctx.precond(torch.tensor(X[i], dtype=torch.complex64, device="cuda"), adjoint=adj)
+                       .cpu().numpy() for i in range(4)])
+        ZB = ctx.precond(torch.tensor(X, dtype=torch.complex64, device="cuda"), adjoint=adj).cpu().numpy()
+        e1, r1 = _rel(z1, ref), _rowmax(z1, ref)
+        eb, rb = _rel(ZB[:4], ref), _rowmax(ZB[:4], ref)
+        _say(f"  adjoint={adj}: 1 RHS rel {e1:.3e} row {r1:.3e}; 64 RHS rel {eb:.3e} row {rb:.3e}")
+        assert e1 < 5e-5 and r1 < 2e-4
+        assert eb < 5e-5 and rb < 2e-4
+    ctx.close()

@@ -34,8 +34,8 @@ def test_library_hankel_matches_oracle():
     assert np.max(np.abs(h - ref) / np.abs(ref)) < 5e-14
 
 
-def _plan(curves, tol=1e-6, prec="block", z=None, dtype="c128"):
-    return HostPlan(curves, KAPPA, 64, tol, prec=prec, z=z, dtype=dtype)
+def _plan(curves, tol=1e-6, prec="block", z=None, dtype="c128", superleaf=0):
+    return HostPlan(curves, KAPPA, 64, tol, prec=prec, z=z, dtype=dtype, superleaf=superleaf)
 
 
 def test_library_entries_match_oracle():
@@ -78,14 +78,16 @@ def test_host_plan_matvec_matches_dense(case, strip4096, spiral4096):
     assert np.linalg.norm(ya - refa) / np.linalg.norm(refa) < 1e-6
 
 
+@pytest.mark.parametrize("superleaf", [2, 3])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("prec", ["block", "paper"])
-def test_host_plan_preconditioner_matches_dense(prec, dtype, spiral4096):
+def test_host_plan_preconditioner_matches_dense(prec, dtype, superleaf, spiral4096):
     """Both dtypes' sweep schedules: with complex64 storage the sweep
     programs at this size keep their vectors and skeletons in LDS, so the
-    rows remapped into the LDS layout are checked here too."""
+    rows remapped into the LDS layout are checked here too; both super-leaf
+    sizes."""
     c, A = spiral4096
-    p = _plan(c, prec=prec, dtype=dtype)
+    p = _plan(c, prec=prec, dtype=dtype, superleaf=superleaf)
     r = inputs.random_complex(4096, 22)
     f = (lambda v, adj=False: efie.precond_block_apply(A, v, 64, adjoint=adj)) if prec == "block" else \
         (lambda v, adj=False: efie.precond_paper_apply(A, v, adjoint=adj))
@@ -143,6 +145,13 @@ def test_invalid_arguments_rejected(n, leaf, tol):
     c = inputs.strip(n)
     with pytest.raises(_capi.HbfError) as e:
         HostPlan(c, KAPPA, leaf, tol)
+    assert e.value.status == _capi.HBF_EINVAL
+
+
+@pytest.mark.parametrize("superleaf", [1, 4])
+def test_unsupported_superleaf_rejected(superleaf):
+    with pytest.raises(_capi.HbfError) as e:
+        HostPlan(inputs.strip(4096), KAPPA, 64, 1e-6, superleaf=superleaf)
     assert e.value.status == _capi.HBF_EINVAL
 
 

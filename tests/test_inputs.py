@@ -48,3 +48,25 @@ def test_plane_wave_unit_amplitude():
     c = inputs.semicircle(256)
     b = inputs.plane_wave_rhs(c, inputs.uniform_angles(4))
     assert b.shape == (4, 256) and np.allclose(np.abs(b), 1)
+
+
+def test_arc_families():
+    for ang in (math.pi / 4, math.pi, 1.9 * math.pi):
+        c = inputs.arc_with_angle(1024, ang)
+        assert c.n_segments == 1024
+        assert np.all(np.abs(_seglen(c) - 0.1) < 1e-4)
+        # endpoints subtend the requested angle at the centre (on the y axis)
+        r = c.meta["radius"]
+        p0, p1 = c.xy[0], c.xy[-1]
+        cy = p0[1] - r * math.sin(math.pi / 2 - ang / 2)
+        a0 = math.atan2(p0[1] - cy, p0[0])
+        a1 = math.atan2(p1[1] - cy, p1[0])
+        assert abs(((a1 - a0) % (2 * math.pi)) - ang) < 1e-9
+    a = inputs.arc_array(2048, 4, gap=2.0)
+    assert a.ncurves == 4 and a.n_segments == 2048
+    assert np.all(np.abs(_seglen(a) - 0.1) < 1e-4)
+    # left to right, separated by the gap
+    for k in range(3):
+        end = a.xy[a.node_off[k + 1] - 1]
+        start = a.xy[a.node_off[k + 1]]
+        assert abs(np.linalg.norm(start - end) - 2.0) < 1e-9 and start[0] > end[0]
