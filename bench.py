@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--no-srhs", action="store_true", help="skip the semicircle seconds-per-RHS comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
-    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch", "matvec_batch", "scale", "iterations"],
+    ap.add_argument("--mode", default="full", choices=["full", "matvec", "precond", "precond_batch", "matvec_batch", "scale", "iterations", "profile"],
                     help="matvec / precond: only the single-RHS apply loop; precond_batch: the nrhs-RHS "
                          "preconditioner loop with the autotuned parameters (for profiling)")
     ap.add_argument("--reps", type=int, default=20)
@@ -158,6 +158,23 @@ def main():
         for k, v in json.loads(args.params).items():
             ctx.tune(k, v)
     x1 = torch.tensor(inputs.random_complex(n, 7), dtype=torch.complex64, device=dev)
+    if args.mode == "profile":
+        # for rocprofv3: a plain copy of known size (the counter calibration
+        # kernel), the single-RHS matvec, then the 64-RHS matvec and
+        # preconditioner, each kernel identifiable by name
+        big = torch.empty(1 << 27, dtype=torch.complex64, device=dev)
+        big2 = torch.empty_like(big)
+        big2.copy_(big)
+        torch.cuda.synchronize()
+        del big, big2
+        t1 = timed_loop(lambda: ctx.matvec(x1), args.reps)
+        XB = torch.tensor(inputs.random_complex((R, n), 8), dtype=torch.complex64, device=dev)
+        tb = timed_loop(lambda: ctx.matvec(XB), 3)
+        tp = timed_loop(lambda: ctx.precond(XB), 2)
+        print(json.dumps({"mode": "profile", "matvec_1rhs_ms": t1 * 1e3, f"matvec_{R}rhs_ms": tb * 1e3,
+                          f"precond_{R}rhs_ms": tp * 1e3, "launches_matvec": st["launches_matvec"],
+                          "apply_bytes_matvec": st["apply_bytes_matvec"]}))
+        return
     if args.mode == "matvec":
         # a plain copy of known size first: the calibration kernel for the HBM counters
         big = torch.empty(1 << 27, dtype=torch.complex64, device=dev)

@@ -132,6 +132,12 @@ typedef struct {
   int64_t apply_bytes_precond;   /* z = P^{-1} r (both sweeps, and s = D t in the block reading) */
   int64_t launches_matvec;       /* kernel launches of one matvec */
   int64_t arena_rows;            /* rows of skeleton vectors (sum of all ID ranks) per RHS */
+  /* One preconditioner application is a chain of dependent steps (Algorithms
+   * 3 and 4 are sequential over the diagonal tree): kernel launches, and the
+   * steps inside them (a subtree program's steps are separated by workgroup
+   * barriers; a stage launch is one step). */
+  int64_t launches_precond;
+  int64_t steps_precond;
 } hbf_stats_t;
 
 /* Build the H-IDBF of A = Z + diag(z) for the curve at wavenumber `kappa`

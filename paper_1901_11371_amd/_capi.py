@@ -42,7 +42,7 @@ class Stats(C.Structure):
                 ("bytes_precond", C.c_int64), ("bytes_workspace", C.c_int64), ("build_seconds", C.c_double),
                 ("scale_re", C.c_double), ("scale_im", C.c_double), ("apply_bytes_matvec", C.c_int64),
                 ("apply_bytes_precond", C.c_int64), ("launches_matvec", C.c_int64),
-                ("arena_rows", C.c_int64)]
+                ("arena_rows", C.c_int64), ("launches_precond", C.c_int64), ("steps_precond", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

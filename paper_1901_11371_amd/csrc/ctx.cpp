@@ -630,6 +630,17 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       const int64_t vec = 2 * N * static_cast<int64_t>(c->elt);
       c->stats.apply_bytes_matvec = schedule_bytes(P, P.mv_fwd, nullptr, c->elt) + vec;
       c->stats.launches_matvec = static_cast<int64_t>(P.mv_fwd.size());
+      int64_t nl = 0, ns = 0;
+      if (c->prec != HBF_PREC_NONE)
+        for (const auto* L : {&c->S.fwd, &c->S.bwd, &c->S.diag}) {
+          if (L == &c->S.diag && c->prec != HBF_PREC_BLOCK_LU) continue;
+          for (const Launch& l : *L) {
+            nl += 1;
+            ns += l.prog ? l.count : 1;
+          }
+        }
+      c->stats.launches_precond = nl;
+      c->stats.steps_precond = ns;
       c->stats.apply_bytes_precond =
           c->prec == HBF_PREC_NONE
               ? vec

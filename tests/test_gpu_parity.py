@@ -245,6 +245,27 @@ def test_superleaf_sizes(torch, spiral, prec, superleaf):
     ctx.close()
 
 
+def test_bitwise_determinism(torch, spiral):
+    """No kernel uses atomics for results and every reduction has a fixed
+    order: repeated products and solves are bit-identical (1 and 64 RHS,
+    forward and adjoint, the matrix-core and the pipelined launches)."""
+    c, _ = spiral
+    ctx = _ctx(c, "c64", max_nrhs=64)
+    X = torch.tensor(inputs.random_complex((64, 4096), 39), dtype=torch.complex64, device="cuda")
+    for Xi in (X, X[5].contiguous()):
+        for adj in (False, True):
+            a1 = ctx.matvec(Xi, adjoint=adj).cpu().numpy()
+            a2 = ctx.matvec(Xi, adjoint=adj).cpu().numpy()
+            p1 = ctx.precond(Xi, adjoint=adj).cpu().numpy()
+            p2 = ctx.precond(Xi, adjoint=adj).cpu().numpy()
+            assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+    B = torch.tensor(inputs.plane_wave_rhs(c, inputs.uniform_angles(3)), device="cuda")
+    x1, i1, _ = ctx.solve(B, tol=1e-6, max_iters=60)
+    x2, i2, _ = ctx.solve(B, tol=1e-6, max_iters=60)
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy()) and i1 == i2
+    ctx.close()
+
+
 def test_nrhs_beyond_max_is_rejected(torch, spiral):
     from paper_1901_11371_amd._capi import HBF_EINVAL, HbfError
     c, _ = spiral

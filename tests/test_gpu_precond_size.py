@@ -51,14 +51,22 @@ def golden14(golden_dir):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("prec", ["block", "paper"])
 def test_precond_spiral_2p14_vs_stored_oracle(torch, golden14, prec, dtype):
+    """The compressed preconditioner differs from the dense one by the ID
+    tolerance amplified by the sweeps, and that grows with N: the host FP64
+    executor of the same factorisation is 3.6e-6 (block) / 5.1e-6 (paper)
+    from these stored values at ID tolerance 1e-6, with single rows up to
+    4.9e-5 of the largest, and 4.8e-8 / 7.5e-8 at 1e-7 (linear in the
+    tolerance).  So the comparison builds at 1e-7, where the bars isolate
+    the sweeps' arithmetic: complex128 within 10x of the host executor,
+    complex64 at its storage precision as at N = 4096."""
     from paper_1901_11371_amd.hbf import Context
     n = 1 << 14
     c = inputs.archimedean_spiral(n)
     _say(f"[precond 2^14] prec={prec} dtype={dtype}")
-    ctx = Context(c, KAPPA, 64, 1e-6, dtype=dtype, prec=prec, max_nrhs=16, cache_plan=True)
+    ctx = Context(c, KAPPA, 64, 1e-7, dtype=dtype, prec=prec, max_nrhs=16, cache_plan=True)
     td = torch.complex64 if dtype == "c64" else torch.complex128
     R = golden14["r"]
-    bar, rowbar = (2e-6, 1e-5) if dtype == "c128" else (5e-5, 2e-4)
+    bar, rowbar = (1e-6, 2e-6) if dtype == "c128" else (5e-5, 2e-4)
     for adj in (False, True):
         ref = golden14[f"{prec}_{'adj' if adj else 'fwd'}"]
         Z = np.stack([ctx.precond(torch.tensor(R[i], dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
