@@ -161,6 +161,17 @@ hbf_status hbf_set_impedance(hbf_ctx* ctx, const double* z_host);
 hbf_status hbf_matvec(hbf_ctx* ctx, const void* x, void* y, int32_t nrhs, hbf_dtype io,
                       int32_t adjoint, void* stream);
 
+/* hbf_matvec without any device allocation or use of the context's
+ * workspace, for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as hbf_matvec.  Its scratch (the skeleton vectors,
+ * arena_rows x nrhs x 16 bytes, plus two (N, nrhs) layout buffers when
+ * nrhs > 1) is one fixed 64 MiB array per device, held until the process
+ * ends; a call that needs more returns HBF_EINVAL.  Every call on a device
+ * shares that array, so calls that overlap on one device race. */
+hbf_status hbf_matvec_noalloc(hbf_ctx* ctx, const void* x, void* y, int32_t nrhs, hbf_dtype io,
+                              int32_t adjoint, void* stream);
+
 /* z = P^{-1} r (adjoint = 0) or z = P^{-H} r (adjoint = 1): block forward
  * substitution over the lower part followed by block back substitution over
  * the upper part (Algorithms 3 and 4), with the leaf solves of the chosen

@@ -54,6 +54,8 @@ SIGNATURES = {
                             C.POINTER(C.c_void_p)]),
     "hbf_set_impedance": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "hbf_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int, C.c_int32, C.c_void_p]),
+    "hbf_matvec_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int, C.c_int32,
+                                     C.c_void_p]),
     "hbf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int, C.c_int32,
                                     C.c_void_p]),
     "hbf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int, C.POINTER(SolveOpts),

@@ -155,6 +155,17 @@ class Context:
                                             xx.shape[0], DTYPE[io], int(adjoint), _stream_ptr(_torch(), self.device)))
         return y.reshape(x.shape)
 
+    def matvec_noalloc(self, x, adjoint=False, io=None):
+        """hbf_matvec_noalloc: the same product with the library's fixed
+        per-device scratch instead of the context's workspace."""
+        io = io or ("c64" if x.dtype == _torch().complex64 else "c128")
+        xx = self._prep(x, io)
+        y = _torch().empty_like(xx)
+        check(self.lib, self.lib.hbf_matvec_noalloc(self.h, C.c_void_p(xx.data_ptr()), C.c_void_p(y.data_ptr()),
+                                                    xx.shape[0], DTYPE[io], int(adjoint),
+                                                    _stream_ptr(_torch(), self.device)))
+        return y.reshape(x.shape)
+
     def precond(self, r, adjoint=False):
         io = self.dtype
         rr = self._prep(r, io)
