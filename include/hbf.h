@@ -228,8 +228,9 @@ hbf_status hbf_impedance_grad(hbf_ctx* ctx, const void* lam, const void* x, int3
  *   "mfma"          1 = complex64 stage launches with nrhs >= mfma_min_r run
  *                   as complex GEMMs on the FP32 matrix cores (default 1),
  *   "mfma_min_r"    smallest nrhs for the matrix-core stage launches (default 8),
- *   "mfma_tiles"    right-hand sides per wave of those launches, in 16-column
- *                   tiles: 1, 2 or 4 (default 4).
+ *   "mfma_tiles"    right-hand sides per wave of the matvec's matrix-core
+ *                   launches, in 16-column tiles: 1, 2 or 4 (default 4),
+ *   "sweep_mfma_tiles"  the same for the sweeps' stage launches (default 1).
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);
 

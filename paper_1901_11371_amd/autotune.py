@@ -29,7 +29,7 @@ import torch
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "autotune.json")
 
 # stage-kernel variants: name -> hbf_tune settings
-_VALU = {"mfma": 0, "mfma_min_r": 8, "mfma_tiles": 4}
+_VALU = {"mfma": 0, "mfma_min_r": 8, "mfma_tiles": 4, "sweep_mfma_tiles": 1}
 _NO_PIPE = {"pipe_max_r": 4, "sweep_pipe_max_r": 4, "wave_units": 1, "sweep_rc1": 0}
 KERNELS = {
     "pipe": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": max(R, 1), "wave_units": 1, "sweep_rc1": 0,
@@ -40,10 +40,11 @@ KERNELS = {
     "pipe+sweep_wave": lambda R: {"pipe_max_r": max(R, 1), "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 0,
                                   **_VALU},
     "wave+rc1": lambda R: {"pipe_max_r": 0, "sweep_pipe_max_r": 0, "wave_units": 1, "sweep_rc1": 1, **_VALU},
-    # matrix-core stage launches with 16, 32 or 64 right-hand sides per wave (complex64 only)
-    "mfma16": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 1},
-    "mfma32": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 2},
-    "mfma64": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 4},
+    # matrix-core stage launches (complex64 only): the matvec at 64 right-hand
+    # sides per wave, the sweeps' launches at 16, 32 or 64
+    "mfma16": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 4, "sweep_mfma_tiles": 1},
+    "mfma32": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 4, "sweep_mfma_tiles": 2},
+    "mfma64": lambda R: {**_NO_PIPE, "mfma": 1, "mfma_min_r": 1, "mfma_tiles": 4, "sweep_mfma_tiles": 4},
 }
 
 

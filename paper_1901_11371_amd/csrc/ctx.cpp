@@ -343,7 +343,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       a.src_cap = 0;
       a.ch = 0;
-      const hipError_t e = launch_stage_mfma_c64(a, l.count, c->mfma_tiles, adj, s);
+      const hipError_t e = launch_stage_mfma_c64(a, l.count, sweep ? c->sweep_mfma_tiles : c->mfma_tiles, adj, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -820,9 +820,9 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     return HBF_OK;
   }
   if (k == "mfma") { c->mfma = value != 0; free_graphs(c); return HBF_OK; }
-  if (k == "mfma_tiles") {
-    if (value != 1 && value != 2 && value != 4) return fail(HBF_EINVAL, "hbf_tune: mfma_tiles must be 1, 2 or 4");
-    c->mfma_tiles = static_cast<int>(value);
+  if (k == "mfma_tiles" || k == "sweep_mfma_tiles") {
+    if (value != 1 && value != 2 && value != 4) return fail(HBF_EINVAL, "hbf_tune: " + k + " must be 1, 2 or 4");
+    (k == "mfma_tiles" ? c->mfma_tiles : c->sweep_mfma_tiles) = static_cast<int>(value);
     free_graphs(c);
     return HBF_OK;
   }

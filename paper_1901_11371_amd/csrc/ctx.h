@@ -32,7 +32,8 @@ struct hbf_ctx {
   int pipe_max_r = 4;          // stage launches with nrhs <= this use the pipelined wave teams
   bool mfma = true;            // complex64 stage launches with nrhs >= mfma_min_r run on the matrix cores
   int mfma_min_r = 8;
-  int mfma_tiles = 4;          // 16-RHS tiles per wave of the matrix-core stage launches (1, 2, 4)
+  int mfma_tiles = 4;          // 16-RHS tiles per wave of the matrix-core matvec launches (1, 2, 4)
+  int sweep_mfma_tiles = 1;    // ... of the sweeps' matrix-core stage launches
   int r1_max_blocks = 0;       // persistent grid size of the stage kernels (0: resident capacity)
 
   // device memory
