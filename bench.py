@@ -52,6 +52,16 @@ def log(*a):
 MATVEC_SOURCES = ("hbf_internal.h", "kernels.h", "plan.cpp", "ctx.cpp", "stage_pipe.hip")
 
 
+def host_cores():
+    """Worker processes for the CPU oracle: the cores this process may run
+    on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def sources_digest():
     """sha256 over the single-RHS matvec's sources (name and contents, in
     name order): identifies the build a set of hardware-counter readings was
@@ -132,7 +142,7 @@ def main():
     log(f"[bench] building spiral N={n} (host construction + upload)")
     t0 = time.time()
     ctx = Context(wl.curves, inputs.KAPPA, wl.n0, wl.tol, dtype="c64", max_nrhs=R, restart=m,
-                  superleaf=args.superleaf)
+                  superleaf=args.superleaf, verbose=True)
     t_build = time.time() - t0
     st = ctx.stats
     log(f"[bench] built in {t_build:.1f}s: mean rank {st['mean_rank']:.2f} max {st['max_rank']} "
@@ -376,7 +386,8 @@ def scale_workload(args):
     dev = torch.device("cuda", 0)
     log(f"[scale] building {wl.curves.ncurves} curves N={n} (host construction + upload)")
     t0 = time.time()
-    ctx = Context(wl.curves, inputs.KAPPA, wl.n0, wl.tol, dtype="c64", max_nrhs=chunk, restart=args.restart)
+    ctx = Context(wl.curves, inputs.KAPPA, wl.n0, wl.tol, dtype="c64", max_nrhs=chunk, restart=args.restart,
+                  verbose=True)
     t_build = time.time() - t0
     st = ctx.stats
     log(f"[scale] built in {t_build:.1f}s: mean rank {st['mean_rank']:.2f} max {st['max_rank']} "
@@ -384,7 +395,7 @@ def scale_workload(args):
         f"leaf inverses {st['bytes_precond']/1e9:.2f} GB workspace {st['bytes_workspace']/1e9:.2f} GB")
     # matvec parity on sampled rows (oracle, one process per core)
     rho, w = efie.segments(wl.curves.xy, wl.curves.node_off)
-    cores = os.cpu_count() or 1
+    cores = host_cores()
     rows = np.sort(np.random.default_rng(inputs.SEED_BASE + 4).choice(n, 2 * cores, replace=False))
     X = inputs.random_complex((2, n), 54)
     Y = ctx.matvec(torch.tensor(X, dtype=torch.complex64, device=dev)).cpu().numpy()
@@ -516,7 +527,7 @@ def cpu_baseline(curves, x_gpu, b, mv_bytes, rows_per_core=12):
 
     from oracle import efie
     from paper_1901_11371_amd import inputs
-    cores = os.cpu_count() or 1
+    cores = host_cores()
     rho, w = efie.segments(curves.xy, curves.node_off)
     n = rho.shape[0]
     rng = np.random.default_rng(inputs.SEED_BASE + 2)

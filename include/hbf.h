@@ -16,7 +16,11 @@
  * Conventions (all entry points):
  *   - Unknowns: one pulse basis function per segment; segment i is the chord
  *     between nodes i and i+1 of the curve (curves concatenated in order).
- *     N must be n0 * 2^V with V >= 1 (leaf size n0 = `leaf`).
+ *     Any N > n0 (leaf size n0 = `leaf`): the leaves are the pieces of the
+ *     bisection of [0, N) with first halves ceil(m/2) down to at most n0
+ *     unknowns (the leaf partition of Algorithms 3 and 4).  Internally N is
+ *     padded to n0 2^V with unknowns that are decoupled from the others
+ *     (identity rows and columns); no padding is visible at the interface.
  *   - Vectors passed to matvec/precond/solve are DEVICE pointers owned by the
  *     caller, shape (nrhs, N), C-contiguous, interleaved re/im
  *     (complex64: 2 x float, complex128: 2 x double), i.e. torch's layout.
@@ -85,6 +89,7 @@ typedef struct {
                          the host construction; 0: no caching (a cache hit is still used) */
   int32_t superleaf;  /* leaf solves of the sweeps invert diagonal blocks of 2^superleaf leaves
                          exactly (2 or 3; <= 0 selects 2) */
+  int32_t verbose;    /* 1: one progress line per construction phase and H-level on stderr */
 } hbf_build_opts;
 
 /* Krylov method of the inner solves. */
@@ -113,7 +118,7 @@ typedef struct {
 } hbf_solve_info;
 
 typedef struct {
-  int64_t n, leaf, levels;       /* N, n0, V = log2(N / n0) */
+  int64_t n, leaf, levels;       /* N, n0, V (the leaf partition's depth) */
   int64_t n_blocks;              /* butterfly-compressed off-diagonal blocks */
   int64_t n_units;               /* small dense operations of one matvec */
   int32_t max_rank;              /* largest skeleton size of any ID */
@@ -138,6 +143,7 @@ typedef struct {
    * barriers; a stage launch is one step). */
   int64_t launches_precond;
   int64_t steps_precond;
+  int64_t n_internal;            /* n0 2^V: N padded with decoupled unknowns (= N when N = n0 2^V) */
 } hbf_stats_t;
 
 /* Build the H-IDBF of A = Z + diag(z) for the curve at wavenumber `kappa`

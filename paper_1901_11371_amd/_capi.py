@@ -21,7 +21,7 @@ class Curve(C.Structure):
 class BuildOpts(C.Structure):
     _fields_ = [("dtype", C.c_int), ("prec", C.c_int), ("eta0", C.c_double), ("z", C.POINTER(C.c_double)),
                 ("max_nrhs", C.c_int32), ("restart", C.c_int32), ("device", C.c_int32), ("nthreads", C.c_int32),
-                ("cache_plan", C.c_int32), ("superleaf", C.c_int32)]
+                ("cache_plan", C.c_int32), ("superleaf", C.c_int32), ("verbose", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -42,7 +42,8 @@ class Stats(C.Structure):
                 ("bytes_precond", C.c_int64), ("bytes_workspace", C.c_int64), ("build_seconds", C.c_double),
                 ("scale_re", C.c_double), ("scale_im", C.c_double), ("apply_bytes_matvec", C.c_int64),
                 ("apply_bytes_precond", C.c_int64), ("launches_matvec", C.c_int64),
-                ("arena_rows", C.c_int64), ("launches_precond", C.c_int64), ("steps_precond", C.c_int64)]
+                ("arena_rows", C.c_int64), ("launches_precond", C.c_int64), ("steps_precond", C.c_int64),
+                ("n_internal", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -73,6 +74,10 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_x64);
   dfree(c->d_red);
   dfree(c->d_small);
+  dfree(c->d_real_of);
+  dfree(c->d_lib_of);
+  c->d_real_of = c->d_lib_of = nullptr;
+  c->vmap = hbf::VecMap{};
   if (c->h_flags) (void)hipHostFree(c->h_flags);
   c->h_flags = nullptr;
   for (auto& e : c->ev_step)
@@ -509,6 +514,13 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     c->restart = (opts && opts->restart > 0) ? std::min(opts->restart, 255) : 30;
     c->device = opts ? opts->device : 0;
     c->elt = c->dtype == HBF_C64 ? 8 : 16;
+    const bool verbose = opts && opts->verbose;
+    auto progress = [&](const char* what) {
+      if (!verbose) return;
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      std::fprintf(stderr, "[hbf] %s (%.1f s)\n", what, sec);
+      std::fflush(stderr);
+    };
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
       (void)hipGetLastError();
@@ -543,7 +555,23 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     }
     Plan& P = c->P;
     c->n = P.n;
+    c->n_ext = P.n_real;
     const int64_t N = P.n;
+    c->vmap.n_int = P.n;
+    c->vmap.n_ext = P.n_real;
+    if (c->padded()) {
+      // device copies of the padding map (library row <-> caller's unknown)
+      std::vector<int32_t> real_of(static_cast<size_t>(P.n), -1);
+      for (int64_t j = 0; j < P.n_real; ++j) real_of[P.lib_of[j]] = static_cast<int32_t>(j);
+      dmalloc(&c->d_real_of, real_of.size() * sizeof(int32_t), "padding map");
+      dmalloc(&c->d_lib_of, P.lib_of.size() * sizeof(int32_t), "padding map");
+      hip_check(hipMemcpy(c->d_real_of, real_of.data(), real_of.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                "padding map");
+      hip_check(hipMemcpy(c->d_lib_of, P.lib_of.data(), P.lib_of.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                "padding map");
+      c->vmap.real_of = c->d_real_of;
+      c->vmap.lib_of = c->d_lib_of;
+    }
     const int n0 = P.n0;
     const int64_t nl = N / n0;
     const int64_t bs = static_cast<int64_t>(n0) * n0;
@@ -598,7 +626,9 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       if (!lu.empty())
         hip_check(hipMemcpy(c->d_lunits, lu.data(), lu.size() * sizeof(Unit), hipMemcpyHostToDevice), "units");
     }
+    progress("factors uploaded");
     rebuild_sweeps(c.get(), c->S.prog_levels);
+    progress("sweep schedules built");
     prepare_launch_shapes();
     const size_t R = static_cast<size_t>(c->max_nrhs);
     const size_t vbytes = static_cast<size_t>(N) * R * 16;
@@ -623,6 +653,7 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
                          static_cast<size_t>(nkry + 1) * N * R * c->elt + 4 * vbytes;
     if (c->prec != HBF_PREC_NONE) superleaf_entries(c.get());
     factor_leaves(c.get(), s);
+    progress("leaf blocks factored");
     // release the host copies of the factors
     fill_stats(P, &c->stats, c->elt);
     c->stats.bytes_index = static_cast<int64_t>(P.perm.size() + P.units.size() * sizeof(Unit));
@@ -678,12 +709,13 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
 
 hbf_status hbf_set_impedance(hbf_ctx* c, const double* z) {
   if (!c || !z) return fail(HBF_EINVAL, "hbf_set_impedance: NULL argument");
-  for (int64_t i = 0; i < 2 * c->n; ++i)
+  for (int64_t i = 0; i < 2 * c->n_ext; ++i)
     if (!std::isfinite(z[i])) return fail(HBF_EINVAL, "hbf_set_impedance: non-finite impedance");
   try {
     hip_check(hipSetDevice(c->device), "hipSetDevice");
-    c->P.z.resize(c->n);
-    for (int64_t i = 0; i < c->n; ++i) c->P.z[i] = cplx(z[2 * i], z[2 * i + 1]);
+    // library order; padding rows keep z = 0 (their diagonal stays 1)
+    c->P.z.assign(c->n, cplx(0.0, 0.0));
+    for (int64_t i = 0; i < c->n_ext; ++i) c->P.z[c->P.lib(i)] = cplx(z[2 * i], z[2 * i + 1]);
     // refresh the dense diagonal units used by the matvec (their matrices hold A_bb)
     const int n0 = c->P.n0;
     const int64_t nl = c->n / n0;
@@ -697,11 +729,12 @@ hbf_status hbf_set_impedance(hbf_ctx* c, const double* z) {
         d.y += c->P.z[b * n0 + i].imag();
       }
     }
-    // the rescaling follows the largest diagonal entry
+    // the rescaling follows the largest diagonal entry of the caller's unknowns
     {
       int64_t ib = 0;
       double best = -1.0;
-      for (int64_t i = 0; i < c->n; ++i) {
+      for (int64_t j = 0; j < c->n_ext; ++j) {
+        const int64_t i = c->P.lib(j);
         const cd& d = D[(i / n0) * bs + (i % n0) * n0 + (i % n0)];
         const double m = std::hypot(d.x, d.y);
         if (m > best) { best = m; ib = i; }
@@ -747,11 +780,11 @@ hbf_status hbf_matvec(hbf_ctx* c, const void* x, void* y, int32_t nrhs, hbf_dtyp
   if (hipSetDevice(c->device) != hipSuccess) return fail(HBF_EHIP, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool v128 = io == HBF_C128;
-  if (nrhs == 1) return matvec_internal(c, const_cast<void*>(x), y, 1, v128, adjoint != 0, s);
-  if (launch_to_internal(x, v128, c->d_vin, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  if (nrhs == 1 && !c->padded()) return matvec_internal(c, const_cast<void*>(x), y, 1, v128, adjoint != 0, s);
+  if (launch_to_internal(x, v128, c->d_vin, v128, c->vmap, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
   hbf_status st = matvec_internal(c, c->d_vin, c->d_vout, nrhs, v128, adjoint != 0, s);
   if (st != HBF_OK) return st;
-  if (launch_to_external(c->d_vout, v128, y, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  if (launch_to_external(c->d_vout, v128, y, v128, c->vmap, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
   return HBF_OK;
 }
 
@@ -763,11 +796,11 @@ hbf_status hbf_precond_apply(hbf_ctx* c, const void* r, void* z, int32_t nrhs, h
   if (hipSetDevice(c->device) != hipSuccess) return fail(HBF_EHIP, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool v128 = io == HBF_C128;
-  if (nrhs == 1) return precond_internal(c, r, z, 1, adjoint != 0, s);
-  if (launch_to_internal(r, v128, c->d_vin, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  if (nrhs == 1 && !c->padded()) return precond_internal(c, r, z, 1, adjoint != 0, s);
+  if (launch_to_internal(r, v128, c->d_vin, v128, c->vmap, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
   hbf_status st = precond_internal(c, c->d_vin, c->d_vout, nrhs, adjoint != 0, s);
   if (st != HBF_OK) return st;
-  if (launch_to_external(c->d_vout, v128, z, v128, c->n, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
+  if (launch_to_external(c->d_vout, v128, z, v128, c->vmap, nrhs, s) != hipSuccess) return fail(HBF_EHIP, "layout");
   return HBF_OK;
 }
 
@@ -857,7 +890,7 @@ hbf_status hbf_stats(const hbf_ctx* c, hbf_stats_t* out) {
   return HBF_OK;
 }
 
-int64_t hbf_size(const hbf_ctx* c) { return c ? c->n : -1; }
+int64_t hbf_size(const hbf_ctx* c) { return c ? c->n_ext : -1; }
 
 void hbf_free(hbf_ctx* c) {
   if (!c) return;

@@ -20,7 +20,12 @@ struct hbf_ctx {
   int device = 0;
   int max_nrhs = 1;
   int restart = 30;
-  int64_t n = 0;
+  int64_t n = 0;                // library rows (padded size)
+  int64_t n_ext = 0;            // the caller's N
+  int32_t* d_real_of = nullptr; // padding map on the device (null when n == N)
+  int32_t* d_lib_of = nullptr;
+  hbf::VecMap vmap;             // conversions between the caller's and the library layout
+  bool padded() const { return n != n_ext; }
   int elt = 8;                 // bytes per factor entry
   bool wave_units = true;      // one wave per group for one- or two-RHS launches
   bool prog_pipe = true;       // pipelined wave teams in the sweep programs
@@ -47,7 +52,7 @@ struct hbf_ctx {
   hbf::Unit* d_lunits = nullptr;  // launch-order unit copies of the direct matvec launches
   std::vector<hbf::Launch> mv_fwd, mv_adj;  // matvec schedules as launched (mv_direct)
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
-  void* d_vin = nullptr;       // internal-layout vectors, N x max_nrhs x 16 bytes each
+  void* d_vin = nullptr;       // internal-layout vectors, n x max_nrhs x 16 bytes each
   void* d_vout = nullptr;
   void* d_u = nullptr;         // preconditioner work
   void* d_t = nullptr;

@@ -105,8 +105,17 @@ struct BlockInfo {
 
 // The whole host-side factorisation.
 struct Plan {
-  // problem
-  int64_t n = 0;
+  // problem.  Unknowns are stored in the library's order: N real unknowns
+  // (the caller's) padded to n = n0 2^V.  The bisection of [0, N) into leaves
+  // of at most n0 (first half ceil(m/2), the leaf partition of Algorithms 3
+  // and 4) places real leaf b at the start of library leaf lib_leaf(b); the
+  // other library rows are ghost unknowns with A = identity on them and no
+  // coupling, so the library operator is A (+) I and its block
+  // preconditioner P (+) I.  For N = n0 2^V the map is the identity.
+  int64_t n = 0;                  // library size n0 2^V
+  int64_t n_real = 0;             // the caller's N
+  std::vector<int32_t> lib_of;    // real index -> library index (empty: identity)
+  std::vector<uint8_t> ghost;     // per library index: 1 for a ghost unknown (empty: none)
   int n0 = 0;
   int V = 0;                 // log2(N / n0)
   double kappa = 0, eta0 = 0, tol = 0;
@@ -147,6 +156,8 @@ struct Plan {
 
   cplx entry(int64_t i, int64_t j) const;
   cplx self_entry(int64_t i) const;
+  bool is_ghost(int64_t i) const { return !ghost.empty() && ghost[i]; }
+  int64_t lib(int64_t i) const { return lib_of.empty() ? i : lib_of[i]; }
 };
 
 // Build the plan (host only).  Throws std::runtime_error on invalid input.

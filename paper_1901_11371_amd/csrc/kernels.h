@@ -81,8 +81,21 @@ hipError_t launch_program_c128(const StageArgs& a, const int32_t* steps, int s0,
                                hipStream_t s);
 
 // (nrhs, N) external layout <-> (N, R) internal layout, with dtype conversion.
-hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, int64_t n, int R, hipStream_t s);
-hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c128, int64_t n, int R, hipStream_t s);
+// The caller's N unknowns and the library's n >= N rows (device arrays; both
+// null when n == N and the order is the identity): real_of[i] is the caller's
+// index of library row i, or -1 for a padding row; lib_of[j] the library row
+// of the caller's unknown j.
+struct VecMap {
+  int64_t n_int = 0, n_ext = 0;
+  const int32_t* real_of = nullptr;
+  const int32_t* lib_of = nullptr;
+};
+// (R, N) caller layout <-> (n, R) library layout with a dtype cast; padding
+// rows of the library layout are written as zero.
+hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, const VecMap& m, int R,
+                              hipStream_t s);
+hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c128, const VecMap& m, int R,
+                              hipStream_t s);
 
 // Super-leaf factorisation in FP64 of super-leaves [S0, S0+nb): A holds their
 // exact diagonal blocks (row-major ns x ns each, batch-local); the inverses of

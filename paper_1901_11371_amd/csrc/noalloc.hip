@@ -54,7 +54,8 @@ extern "C" hbf_status hbf_matvec_noalloc(hbf_ctx* c, const void* x, void* y, int
   const size_t R = static_cast<size_t>(nrhs);
   const size_t io_elt = io == HBF_C128 ? 16 : 8;
   const size_t arena = align256(static_cast<size_t>(std::max<int64_t>(c->P.arena_rows, 1)) * R * 16);
-  const size_t vec = nrhs > 1 ? align256(static_cast<size_t>(c->n) * R * io_elt) : 0;
+  const bool convert = nrhs > 1 || c->padded();
+  const size_t vec = convert ? align256(static_cast<size_t>(c->n) * R * io_elt) : 0;
   if (arena + 2 * vec > kScratchBytes)
     return fail(HBF_EINVAL, "hbf_matvec_noalloc: needs " + std::to_string(arena + 2 * vec) +
                                 " bytes of scratch, more than its fixed 64 MiB (use hbf_matvec)");
@@ -65,14 +66,14 @@ extern "C" hbf_status hbf_matvec_noalloc(hbf_ctx* c, const void* x, void* y, int
   char* p = static_cast<char*>(base);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool v128 = io == HBF_C128;
-  if (nrhs == 1) return hbf::matvec_internal(c, const_cast<void*>(x), y, 1, v128, adjoint != 0, s, p);
+  if (!convert) return hbf::matvec_internal(c, const_cast<void*>(x), y, 1, v128, adjoint != 0, s, p);
   void* vin = p + arena;
   void* vout = p + arena + vec;
-  if (hbf::launch_to_internal(x, v128, vin, v128, c->n, nrhs, s) != hipSuccess)
+  if (hbf::launch_to_internal(x, v128, vin, v128, c->vmap, nrhs, s) != hipSuccess)
     return fail(HBF_EHIP, "hbf_matvec_noalloc: layout");
   const hbf_status st = hbf::matvec_internal(c, vin, vout, nrhs, v128, adjoint != 0, s, p);
   if (st != HBF_OK) return st;
-  if (hbf::launch_to_external(vout, v128, y, v128, c->n, nrhs, s) != hipSuccess)
+  if (hbf::launch_to_external(vout, v128, y, v128, c->vmap, nrhs, s) != hipSuccess)
     return fail(HBF_EHIP, "hbf_matvec_noalloc: layout");
   return HBF_OK;
 }

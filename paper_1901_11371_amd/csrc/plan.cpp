@@ -18,6 +18,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <stdexcept>
@@ -84,6 +85,14 @@ void mock_cheb(int64_t lo, int64_t n, int s, std::vector<int32_t>& out) {
   std::sort(idx.begin(), idx.end());
   idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
   for (int64_t i : idx) out.push_back(static_cast<int32_t>(lo + i));
+}
+
+// The real unknowns of the library range [lo, lo+n) in order (ghost
+// entries of the matrix are zero, so samples are drawn from these only).
+void real_indices(const Plan& P, int64_t lo, int64_t n, std::vector<int32_t>& out) {
+  out.clear();
+  for (int64_t i = lo; i < lo + n; ++i)
+    if (!P.is_ghost(i)) out.push_back(static_cast<int32_t>(i));
 }
 
 struct IdRec {
@@ -218,36 +227,59 @@ void compute_id(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, in
     seed ^= seed >> 31;
     return seed;
   };
+  // the partner set: its real unknowns, addressed by position pos[0..pr)
+  std::vector<int32_t> pos;
+  const bool padded = !P.ghost.empty();
+  if (padded) real_indices(P, plo, pn, pos);
+  const int64_t pr = padded ? static_cast<int64_t>(pos.size()) : pn;
+  if (pr == 0) {  // nothing to interpolate against: every candidate is redundant with T = 0
+    out.k = 0;
+    out.perm.resize(n);
+    for (int c = 0; c < n; ++c) out.perm[c] = c;
+    out.T.assign(0, cplx(0.0));
+    out.skel.clear();
+    return;
+  }
+  auto to_partner = [&](std::vector<int32_t>& v) {
+    if (padded)
+      for (auto& x : v) x = pos[x];
+    else
+      for (auto& x : v) x += static_cast<int32_t>(plo);
+  };
+  s = static_cast<int>(std::min<int64_t>(pr, s));
   for (int attempt = 0; attempt < 8; ++attempt) {
-    mock_cheb(plo, pn, s, samp);
+    mock_cheb(0, pr, s, samp);
+    to_partner(samp);
     const int ss = static_cast<int>(samp.size());
     fill(samp, M);
     column_id(M, ss, n, eps, std::min(n, 127), out);
-    if (ss >= pn) break;
+    if (ss >= pr) break;
     const int need = 2 * out.k + 16;
     if (ss < need) {
-      s = static_cast<int>(std::min<int64_t>(pn, need + 16));
+      s = static_cast<int>(std::min<int64_t>(pr, need + 16));
       continue;
     }
     // probe: residual of K(probe, p) - K(probe, q) T relative to K(probe, cand)
     const int np = 16;
     probe.resize(np);
-    for (int a = 0; a < np; ++a) probe[a] = static_cast<int32_t>(plo + static_cast<int64_t>(rnd() % pn));
+    for (int a = 0; a < np; ++a) probe[a] = static_cast<int32_t>(rnd() % pr);
+    to_partner(probe);
+    const int npr = np;
     fill(probe, Mp);
     const int k = out.k, r = n - k;
     double rn = 0.0, an = 0.0;
     for (int c = 0; c < n; ++c)
-      for (int a = 0; a < np; ++a) an += std::norm(Mp[static_cast<size_t>(c) * np + a]);
+      for (int a = 0; a < npr; ++a) an += std::norm(Mp[static_cast<size_t>(c) * npr + a]);
     for (int t = 0; t < r; ++t) {
       const int pc = out.perm[k + t];
-      for (int a = 0; a < np; ++a) {
-        cplx acc = Mp[static_cast<size_t>(pc) * np + a];
-        for (int i = 0; i < k; ++i) acc -= Mp[static_cast<size_t>(out.perm[i]) * np + a] * out.T[static_cast<size_t>(i) * r + t];
+      for (int a = 0; a < npr; ++a) {
+        cplx acc = Mp[static_cast<size_t>(pc) * npr + a];
+        for (int i = 0; i < k; ++i) acc -= Mp[static_cast<size_t>(out.perm[i]) * npr + a] * out.T[static_cast<size_t>(i) * r + t];
         rn += std::norm(acc);
       }
     }
     if (rn <= 4.0 * eps * eps * an) break;
-    s = static_cast<int>(std::min<int64_t>(pn, 2 * ss));
+    s = static_cast<int>(std::min<int64_t>(pr, 2 * ss));
   }
   out.skel.resize(out.k);
   for (int i = 0; i < out.k; ++i) out.skel[i] = cand[out.perm[i]];
@@ -591,6 +623,7 @@ int build_threads(const hbf_build_opts* opts) {
 }
 
 cplx Plan::self_entry(int64_t i) const {
+  if (is_ghost(i)) return cplx(1.0, 0.0);
   // Sec. 3.1 closed form: (kappa eta0 w_i / 4) [1 - i (2/pi) ln(gamma kappa w_i / (4 e))]
   const double g = std::exp(kEulerGamma);
   const double c = kappa * eta0 * w[i] / 4.0;
@@ -601,6 +634,7 @@ cplx Plan::self_entry(int64_t i) const {
 
 cplx Plan::entry(int64_t i, int64_t j) const {
   if (i == j) return self_entry(i);
+  if (is_ghost(i) || is_ghost(j)) return cplx(0.0, 0.0);
   const double r = std::hypot(cx[i] - cx[j], cy[i] - cy[j]);
   return (kappa * eta0 * w[j] / 4.0) * hankel2_0(kappa * r);
 }
@@ -631,20 +665,60 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
       P.w.push_back(wl);
     }
   }
-  P.n = static_cast<int64_t>(P.w.size());
+  P.n_real = static_cast<int64_t>(P.w.size());
   P.n0 = leaf;
-  if (P.n % leaf != 0) throw std::invalid_argument("hbf_build: N must be leaf * 2^V");
+  if (P.n_real <= leaf) throw std::invalid_argument("hbf_build: N must exceed the leaf size");
+  if (P.n_real >= (int64_t(1) << 29)) throw std::invalid_argument("hbf_build: N too large");
+  {
+    // leaf partition: bisect [0, N) while a piece has more than n0 unknowns,
+    // first half ceil(m/2); a leaf at depth d and index j of that tree owns
+    // library leaf j 2^(V - d), V the deepest level
+    struct Leaf { int64_t lo, hi; int depth; int64_t index; };
+    std::vector<Leaf> leaves;
+    std::function<void(int64_t, int64_t, int, int64_t)> rec = [&](int64_t lo, int64_t hi, int d, int64_t j) {
+      if (hi - lo <= leaf) {
+        leaves.push_back({lo, hi, d, j});
+        return;
+      }
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      rec(lo, mid, d + 1, 2 * j);
+      rec(mid, hi, d + 1, 2 * j + 1);
+    };
+    rec(0, P.n_real, 0, 0);
+    int V = 0;
+    for (const Leaf& l : leaves) V = std::max(V, l.depth);
+    P.V = V;
+    P.n = static_cast<int64_t>(leaf) << V;
+    P.lib_of.clear();
+    P.ghost.clear();
+    if (P.n != P.n_real) {
+      P.lib_of.assign(P.n_real, -1);
+      P.ghost.assign(P.n, 1);
+      std::vector<double> cx(P.n, 0.0), cy(P.n, 0.0), w(P.n, 1.0);
+      for (const Leaf& l : leaves) {
+        const int64_t base = (l.index << (V - l.depth)) * leaf;
+        for (int64_t i = l.lo; i < l.hi; ++i) {
+          const int64_t q = base + (i - l.lo);
+          P.lib_of[i] = static_cast<int32_t>(q);
+          P.ghost[q] = 0;
+          cx[q] = P.cx[i];
+          cy[q] = P.cy[i];
+          w[q] = P.w[i];
+        }
+      }
+      P.cx.swap(cx);
+      P.cy.swap(cy);
+      P.w.swap(w);
+    }
+  }
   const int64_t nl = P.n / leaf;
-  if (nl < 2 || (nl & (nl - 1)) != 0) throw std::invalid_argument("hbf_build: N must be leaf * 2^V with V >= 1");
-  if (P.n >= (int64_t(1) << 30)) throw std::invalid_argument("hbf_build: N too large");
-  P.V = ilog2(nl);
   P.kappa = kappa;
   P.eta0 = (opts && opts->eta0 > 0.0) ? opts->eta0 : 376.730313668;
   P.tol = tol;
   P.z.clear();
   if (opts && opts->z) {
-    P.z.resize(P.n);
-    for (int64_t i = 0; i < P.n; ++i) P.z[i] = cplx(opts->z[2 * i], opts->z[2 * i + 1]);
+    P.z.assign(P.n, cplx(0.0, 0.0));
+    for (int64_t i = 0; i < P.n_real; ++i) P.z[P.lib(i)] = cplx(opts->z[2 * i], opts->z[2 * i + 1]);
   }
   const int nthreads = build_threads(opts);
   // the ID tolerance: a fraction of tol, so the accumulated error over the
@@ -674,17 +748,27 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
   }
   const int64_t dense_end = static_cast<int64_t>(P.fac.size());
   // butterfly blocks, H-level by H-level
-  for (int v = 1; v < P.V; ++v) build_level_blocks(P, v, eps, nthreads);
+  const bool verbose = opts && opts->verbose;
+  for (int v = 1; v < P.V; ++v) {
+    build_level_blocks(P, v, eps, nthreads);
+    if (verbose) {
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      std::fprintf(stderr, "[hbf] H-level %d of %d compressed: %zu units, %.2f GB of factors (%.1f s)\n", v, P.V - 1,
+                   P.units.size(), static_cast<double>(P.fac.size()) * 16e-9, sec);
+      std::fflush(stderr);
+    }
+  }
   P.bytes_dense_c128 = dense_end * 16;
   P.bytes_butterfly_c128 = (static_cast<int64_t>(P.fac.size()) - dense_end) * 16;
 
-  // scale factor a = 1 / A[i*, i*], i* = argmax |A_ii| (lowest index on ties)
+  // scale factor a = 1 / A[i*, i*], i* = argmax |A_ii| over the real
+  // unknowns (lowest index on ties)
   {
     int64_t ib = 0;
     double best = -1.0;
-    for (int64_t i = 0; i < P.n; ++i) {
-      const double a = std::abs(P.self_entry(i));
-      if (a > best) { best = a; ib = i; }
+    for (int64_t i = 0; i < P.n_real; ++i) {
+      const double a = std::abs(P.self_entry(P.lib(i)));
+      if (a > best) { best = a; ib = P.lib(i); }
     }
     P.scale = 1.0 / P.self_entry(ib);
   }

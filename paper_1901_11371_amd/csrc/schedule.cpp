@@ -691,17 +691,17 @@ hbf_status hbf_plan_build(const hbf_curve* curve, double kappa, int32_t leaf, do
 hbf_status hbf_plan_apply(const hbf_plan* plan, const double* x, double* y, int32_t nrhs, int32_t adjoint) {
   if (!plan || !x || !y || nrhs < 1) { set_error("hbf_plan_apply: bad arguments"); return HBF_EINVAL; }
   const Plan& P = plan->P;
-  const int64_t N = P.n;
-  // internal layout (N, R)
+  const int64_t N = P.n, NE = P.n_real;
+  // internal layout (N, R) in library order (ghost rows zero)
   std::vector<cplx> xi(N * nrhs), yi(N * nrhs), arena(P.arena_rows * nrhs);
   for (int r = 0; r < nrhs; ++r)
-    for (int64_t i = 0; i < N; ++i) xi[i * nrhs + r] = cplx(x[2 * (r * N + i)], x[2 * (r * N + i) + 1]);
+    for (int64_t i = 0; i < NE; ++i) xi[P.lib(i) * nrhs + r] = cplx(x[2 * (r * NE + i)], x[2 * (r * NE + i) + 1]);
   if (!adjoint) exec_host(P, P.mv_fwd, false, xi.data(), yi.data(), arena.data(), nrhs, 0.0);
   else exec_host(P, P.mv_adj, true, yi.data(), xi.data(), arena.data(), nrhs, 0.0);
   for (int r = 0; r < nrhs; ++r)
-    for (int64_t i = 0; i < N; ++i) {
-      y[2 * (r * N + i)] = yi[i * nrhs + r].real();
-      y[2 * (r * N + i) + 1] = yi[i * nrhs + r].imag();
+    for (int64_t i = 0; i < NE; ++i) {
+      y[2 * (r * NE + i)] = yi[P.lib(i) * nrhs + r].real();
+      y[2 * (r * NE + i) + 1] = yi[P.lib(i) * nrhs + r].imag();
     }
   return HBF_OK;
 }
@@ -710,10 +710,11 @@ hbf_status hbf_plan_precond(const hbf_plan* plan, const double* rin, double* zou
   if (!plan || !rin || !zout || nrhs < 1) { set_error("hbf_plan_precond: bad arguments"); return HBF_EINVAL; }
   const Plan& P = plan->P;
   const Sweeps& S = plan->S;
-  const int64_t N = P.n;
+  const int64_t N = P.n, NE = P.n_real;
   std::vector<cplx> u(N * nrhs), t(N * nrhs), z(N * nrhs), arena(P.arena_rows * nrhs);
   for (int r = 0; r < nrhs; ++r)
-    for (int64_t i = 0; i < N; ++i) u[i * nrhs + r] = cplx(rin[2 * (r * N + i)], rin[2 * (r * N + i) + 1]);
+    for (int64_t i = 0; i < NE; ++i)
+      u[P.lib(i) * nrhs + r] = cplx(rin[2 * (r * NE + i)], rin[2 * (r * NE + i) + 1]);
   if (plan->prec == HBF_PREC_NONE) {
     z = u;
   } else {
@@ -732,9 +733,9 @@ hbf_status hbf_plan_precond(const hbf_plan* plan, const double* rin, double* zou
     }
   }
   for (int r = 0; r < nrhs; ++r)
-    for (int64_t i = 0; i < N; ++i) {
-      zout[2 * (r * N + i)] = z[i * nrhs + r].real();
-      zout[2 * (r * N + i) + 1] = z[i * nrhs + r].imag();
+    for (int64_t i = 0; i < NE; ++i) {
+      zout[2 * (r * NE + i)] = z[P.lib(i) * nrhs + r].real();
+      zout[2 * (r * NE + i) + 1] = z[P.lib(i) * nrhs + r].imag();
     }
   return HBF_OK;
 }
@@ -744,11 +745,11 @@ hbf_status hbf_plan_entries(const hbf_plan* plan, const int64_t* rows, int64_t n
   if (!plan || !rows || !cols || !out) { set_error("hbf_plan_entries: bad arguments"); return HBF_EINVAL; }
   for (int64_t a = 0; a < nr; ++a)
     for (int64_t b = 0; b < nc; ++b) {
-      if (rows[a] < 0 || rows[a] >= plan->P.n || cols[b] < 0 || cols[b] >= plan->P.n) {
+      if (rows[a] < 0 || rows[a] >= plan->P.n_real || cols[b] < 0 || cols[b] >= plan->P.n_real) {
         set_error("hbf_plan_entries: index out of range");
         return HBF_EINVAL;
       }
-      const cplx e = plan->P.entry(rows[a], cols[b]);
+      const cplx e = plan->P.entry(plan->P.lib(rows[a]), plan->P.lib(cols[b]));
       out[2 * (a * nc + b)] = e.real();
       out[2 * (a * nc + b) + 1] = e.imag();
     }
@@ -757,7 +758,8 @@ hbf_status hbf_plan_entries(const hbf_plan* plan, const int64_t* rows, int64_t n
 
 void fill_stats(const Plan& P, hbf_stats_t* s, int elt) {
   std::memset(s, 0, sizeof(*s));
-  s->n = P.n;
+  s->n = P.n_real;
+  s->n_internal = P.n;
   s->leaf = P.n0;
   s->levels = P.V;
   s->n_blocks = static_cast<int64_t>(P.blocks.size());

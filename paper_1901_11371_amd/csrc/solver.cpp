@@ -305,7 +305,7 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
     S.plen = c->red_len / 2;
     S.ielt = c->elt;
 
-    chk(launch_to_internal(b, io == HBF_C128, b64, 1, N, R, s), "layout");
+    chk(launch_to_internal(b, io == HBF_C128, b64, 1, c->vmap, R, s), "layout");
     chk(gm_set_int(c->d_flag, 0, s), "flag");
     chk(gm_nonfinite(true, b64, NR, c->d_flag, s), "check");
     int flag = 0;
@@ -314,7 +314,7 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
     if (flag) throw Err{HBF_EINVAL, std::string(name) + ": non-finite value in the right-hand side"};
     bool x_zero = true;
     if (o.x0_given) {
-      chk(launch_to_internal(x, io == HBF_C128, x64, 1, N, R, s), "layout");
+      chk(launch_to_internal(x, io == HBF_C128, x64, 1, c->vmap, R, s), "layout");
       x_zero = false;
     } else {
       chk(gm_zero(x64, 2 * NR, s), "zero");
@@ -388,7 +388,7 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
       x_zero = false;
       ++refine;
     }
-    chk(launch_to_external(x64, 1, x, io == HBF_C128, N, R, s), "layout");
+    chk(launch_to_external(x64, 1, x, io == HBF_C128, c->vmap, R, s), "layout");
     chk(hipStreamSynchronize(s), "sync");
     if (info) {
       for (int r = 0; r < R; ++r) {
@@ -438,7 +438,7 @@ hbf_status hbf_impedance_grad(hbf_ctx* c, const void* lam, const void* x, int32_
   if (nrhs < 1) { set_error("hbf_impedance_grad: nrhs must be >= 1"); return HBF_EINVAL; }
   if (io != HBF_C64 && io != HBF_C128) { set_error("hbf_impedance_grad: bad io dtype"); return HBF_EINVAL; }
   if (hipSetDevice(c->device) != hipSuccess) { set_error("hipSetDevice"); return HBF_EHIP; }
-  const hipError_t e = gm_impedance_grad(io == HBF_C128, lam, x, c->n, nrhs, grad_z, static_cast<hipStream_t>(stream));
+  const hipError_t e = gm_impedance_grad(io == HBF_C128, lam, x, c->n_ext, nrhs, grad_z, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) { set_error(std::string("hbf_impedance_grad: ") + hipGetErrorString(e)); return HBF_EHIP; }
   return HBF_OK;
 }

@@ -377,23 +377,26 @@ hipError_t launch_stage(const StageArgs& a, int ngroups, bool adjoint, size_t ld
 }
 
 // ---------------------------------------------------------------------------
-// layout conversion (nrhs, N) <-> (N, R) with dtype cast
+// layout conversion (nrhs, N) <-> (n, R) with dtype cast and the padding map
 // ---------------------------------------------------------------------------
 template <class S, class D>
-__global__ void k_to_internal(const cx<S>* ext, cx<D>* in, int64_t n, int R) {
+__global__ void k_to_internal(const cx<S>* ext, cx<D>* in, int64_t n, int64_t n_ext, int R, const int32_t* real_of) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= n * R) return;
   const int64_t i = e / R;
   const int r = static_cast<int>(e - i * R);
-  const cx<S> v = ext[static_cast<int64_t>(r) * n + i];
+  const int64_t j = real_of ? real_of[i] : i;
+  cx<S> v{0, 0};
+  if (j >= 0) v = ext[static_cast<int64_t>(r) * n_ext + j];
   in[e] = cx<D>{static_cast<D>(v.x), static_cast<D>(v.y)};
 }
 template <class S, class D>
-__global__ void k_to_external(const cx<S>* in, cx<D>* ext, int64_t n, int R) {
+__global__ void k_to_external(const cx<S>* in, cx<D>* ext, int64_t n_ext, int R, const int32_t* lib_of) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= n * R) return;
-  const int r = static_cast<int>(e / n);
-  const int64_t i = e - static_cast<int64_t>(r) * n;
+  if (e >= n_ext * R) return;
+  const int r = static_cast<int>(e / n_ext);
+  const int64_t j = e - static_cast<int64_t>(r) * n_ext;
+  const int64_t i = lib_of ? lib_of[j] : j;
   const cx<S> v = in[i * R + r];
   ext[e] = cx<D>{static_cast<D>(v.x), static_cast<D>(v.y)};
 }
@@ -582,23 +585,38 @@ hipError_t launch_program_c128(const StageArgs& a, const int32_t* steps, int s0,
   return launch_program<double, cd, double>(a, steps, s0, s1, wave_lds, adjoint, s);
 }
 
-hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, int64_t n, int R, hipStream_t s) {
+hipError_t launch_to_internal(const void* ext, int ext_c128, void* in, int in_c128, const VecMap& m, int R,
+                              hipStream_t s) {
+  const int64_t n = m.n_int, ne = m.n_ext;
+  const int32_t* map = m.real_of;
   const unsigned nb = blocks_for(n * R, 256);
-  if (ext_c128 && in_c128) hipLaunchKernelGGL((k_to_internal<double, double>), nb, 256, 0, s, (const cd*)ext, (cd*)in, n, R);
-  else if (ext_c128) hipLaunchKernelGGL((k_to_internal<double, float>), nb, 256, 0, s, (const cd*)ext, (cf*)in, n, R);
-  else if (in_c128) hipLaunchKernelGGL((k_to_internal<float, double>), nb, 256, 0, s, (const cf*)ext, (cd*)in, n, R);
-  else hipLaunchKernelGGL((k_to_internal<float, float>), nb, 256, 0, s, (const cf*)ext, (cf*)in, n, R);
+  if (ext_c128 && in_c128)
+    hipLaunchKernelGGL((k_to_internal<double, double>), nb, 256, 0, s, (const cd*)ext, (cd*)in, n, ne, R, map);
+  else if (ext_c128)
+    hipLaunchKernelGGL((k_to_internal<double, float>), nb, 256, 0, s, (const cd*)ext, (cf*)in, n, ne, R, map);
+  else if (in_c128)
+    hipLaunchKernelGGL((k_to_internal<float, double>), nb, 256, 0, s, (const cf*)ext, (cd*)in, n, ne, R, map);
+  else
+    hipLaunchKernelGGL((k_to_internal<float, float>), nb, 256, 0, s, (const cf*)ext, (cf*)in, n, ne, R, map);
   return hipGetLastError();
 }
 
-hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c128, int64_t n, int R, hipStream_t s) {
-  const unsigned nb = blocks_for(n * R, 256);
-  if (ext_c128 && in_c128) hipLaunchKernelGGL((k_to_external<double, double>), nb, 256, 0, s, (const cd*)in, (cd*)ext, n, R);
-  else if (ext_c128) hipLaunchKernelGGL((k_to_external<float, double>), nb, 256, 0, s, (const cf*)in, (cd*)ext, n, R);
-  else if (in_c128) hipLaunchKernelGGL((k_to_external<double, float>), nb, 256, 0, s, (const cd*)in, (cf*)ext, n, R);
-  else hipLaunchKernelGGL((k_to_external<float, float>), nb, 256, 0, s, (const cf*)in, (cf*)ext, n, R);
+hipError_t launch_to_external(const void* in, int in_c128, void* ext, int ext_c128, const VecMap& m, int R,
+                              hipStream_t s) {
+  const int64_t ne = m.n_ext;
+  const int32_t* map = m.lib_of;
+  const unsigned nb = blocks_for(ne * R, 256);
+  if (ext_c128 && in_c128)
+    hipLaunchKernelGGL((k_to_external<double, double>), nb, 256, 0, s, (const cd*)in, (cd*)ext, ne, R, map);
+  else if (ext_c128)
+    hipLaunchKernelGGL((k_to_external<float, double>), nb, 256, 0, s, (const cf*)in, (cd*)ext, ne, R, map);
+  else if (in_c128)
+    hipLaunchKernelGGL((k_to_external<double, float>), nb, 256, 0, s, (const cd*)in, (cf*)ext, ne, R, map);
+  else
+    hipLaunchKernelGGL((k_to_external<float, float>), nb, 256, 0, s, (const cf*)in, (cf*)ext, ne, R, map);
   return hipGetLastError();
 }
+
 
 hipError_t launch_superleaf_factor(const cd* A, int64_t S0, int64_t nb, int ns, int n0, int mode, double sre,
                                   double sim, void* fac, int fac_c128, SuperleafOut so, int* flag, cd* work,

@@ -29,7 +29,7 @@ def _curve_struct(curves):
 
 
 def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, nthreads=0, eta0=0.0,
-          cache_plan=0, superleaf=0):
+          cache_plan=0, superleaf=0, verbose=0):
     keep = []
     zp = None
     if z is not None:
@@ -37,7 +37,7 @@ def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, n
         keep.append(zz)
         zp = zz.ctypes.data_as(C.POINTER(C.c_double))
     o = _capi.BuildOpts(DTYPE[dtype], PREC[prec], eta0, zp, max_nrhs, restart, device, nthreads, cache_plan,
-                        superleaf)
+                        superleaf, int(verbose))
     return o, keep
 
 
@@ -115,7 +115,7 @@ class Context:
     device, shape (N,) or (nrhs, N), complex64 or complex128."""
 
     def __init__(self, curves, kappa, leaf, tol, dtype="c64", prec="block", z=None, max_nrhs=1, restart=30,
-                 device=0, nthreads=0, cache_plan=False, superleaf=0):
+                 device=0, nthreads=0, cache_plan=False, superleaf=0, verbose=False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("hbf.Context needs a HIP device")
@@ -123,7 +123,7 @@ class Context:
         self.device = torch.device("cuda", device)
         cs, keep = _curve_struct(curves)
         o, k2 = _opts(dtype, prec, z, max_nrhs=max_nrhs, restart=restart, device=device, nthreads=nthreads,
-                      cache_plan=int(cache_plan), superleaf=superleaf)
+                      cache_plan=int(cache_plan), superleaf=superleaf, verbose=verbose)
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))
         del keep, k2
@@ -226,6 +226,8 @@ class Context:
 
     def set_impedance(self, z):
         zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
+        if zz.size != 2 * self.n:
+            raise ValueError(f"impedance needs {self.n} values, got {zz.size // 2}")
         check(self.lib, self.lib.hbf_set_impedance(self.h, zz.ctypes.data_as(C.POINTER(C.c_double))))
         st = _capi.Stats()
         check(self.lib, self.lib.hbf_stats(self.h, C.byref(st)))

@@ -296,6 +296,70 @@ def test_impedance_and_refactor(torch):
     ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_any_size_matches_oracle(torch, dtype):
+    """N = 2049 on the spiral: not n0 2^V, leaves at two depths of the
+    bisection, padded to 4096 inside the library.  Matvec and preconditioner
+    (forward, adjoint; 1 and 3 right-hand sides), the allocation-free matvec,
+    an impedance set after construction, and the impedance gradient's
+    length, against the dense oracle."""
+    n = 2049
+    _say(f"[any N] spiral N={n} dtype={dtype}")
+    c = inputs.archimedean_spiral(n)
+    rho, w = efie.segments(c.xy, c.node_off)
+    A = efie.dense_A(rho, w, KAPPA)
+    ctx = _ctx(c, dtype)
+    assert ctx.n == n and ctx.stats["n_internal"] == 4096
+    td = torch.complex64 if dtype == "c64" else torch.complex128
+    X = inputs.random_complex((3, n), 45)
+    for adj in (False, True):
+        Ae = A.conj().T if adj else A
+        for xs in (X[0], X):
+            y = ctx.matvec(torch.tensor(xs, dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
+            ref = (Ae @ xs.T).T
+            assert _rel(y, ref) < 5e-6 and _rowmax(y, ref) < 2e-5, (adj, xs.ndim)
+            zp = ctx.precond(torch.tensor(xs, dtype=td, device="cuda"), adjoint=adj).cpu().numpy()
+            zr = np.stack([efie.precond_block_apply(A, v, 64, adjoint=adj) for v in np.atleast_2d(xs)])
+            assert _rel(np.atleast_2d(zp), zr) < 5e-6, (adj, xs.ndim)
+    y1 = ctx.matvec(torch.tensor(X[0], dtype=td, device="cuda")).cpu().numpy()
+    y2 = ctx.matvec_noalloc(torch.tensor(X[0], dtype=td, device="cuda")).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    z = inputs.impedance(n, 8)
+    ctx.set_impedance(z)
+    Az = efie.dense_A(rho, w, KAPPA, z=z)
+    y = ctx.matvec(torch.tensor(X, dtype=td, device="cuda")).cpu().numpy()
+    assert _rel(y, (Az @ X.T).T) < 5e-6
+    g = ctx.impedance_grad(torch.tensor(X, dtype=td, device="cuda"), torch.tensor(X, dtype=td, device="cuda"))
+    assert g.shape == (n,)
+    ref = -np.sum(X * np.conj(X), axis=0)
+    assert _rel(g.cpu().numpy(), ref) < 1e-6
+    with pytest.raises(ValueError):
+        ctx.set_impedance(np.zeros(4096))
+    ctx.close()
+
+
+def test_any_size_solve_matches_dense_lu(torch):
+    """Batched complex64 solve with FP64 refinement at N = 1000 (padded to
+    1024), 3 plane waves, GMRES and TFQMR, against dense LU."""
+    from paper_1901_11371_amd.hbf import Context
+    n = 1000
+    _say(f"[any N] semicircle N={n} solve")
+    c = inputs.semicircle(n)
+    rho, w = efie.segments(c.xy, c.node_off)
+    A = efie.dense_A(rho, w, KAPPA)
+    B = inputs.plane_wave_rhs(c, inputs.uniform_angles(3))
+    Xr = efie.lu_solve(A, B.T).T
+    ctx = Context(c, KAPPA, 64, 1e-6, dtype="c64", max_nrhs=4)
+    for method in ("gmres", "tfqmr"):
+        X, info, st = ctx.solve(torch.tensor(B, device="cuda"), tol=1e-7, max_iters=300, method=method)
+        X = X.cpu().numpy()
+        errs = [_rel(X[r], Xr[r]) for r in range(3)]
+        _say(f"  {method}: errs max {max(errs):.2e} iters {[i['iters'] for i in info]}")
+        assert st == 0 and all(i["converged"] for i in info)
+        assert max(errs) < 1e-5
+    ctx.close()
+
+
 def test_singular_leaf_and_allocation_failure_are_reported(torch):
     """A leaf whose paper-reading upper factor has an exact zero on its
     diagonal (impedance z_i = -Z_ii, taken from the library's own entries) is

@@ -139,7 +139,7 @@ def test_smallest_hierarchy():
     assert p.stats["n_blocks"] == 0
 
 
-@pytest.mark.parametrize("n,leaf,tol", [(4000, 64, 1e-6), (64, 64, 1e-6), (4096, 1, 1e-6), (4096, 64, 0.0),
+@pytest.mark.parametrize("n,leaf,tol", [(64, 64, 1e-6), (40, 64, 1e-6), (4096, 1, 1e-6), (4096, 64, 0.0),
                                         (4096, 64, 1.5)])
 def test_invalid_arguments_rejected(n, leaf, tol):
     c = inputs.strip(n)
@@ -177,3 +177,44 @@ def test_storage_scales_as_n_log2_squared():
         dense_ratios.append(b / n ** 1.5)
     assert max(ratios) / min(ratios) < 1.6, ratios
     assert all(dense_ratios[i + 1] < dense_ratios[i] for i in range(len(dense_ratios) - 1)), dense_ratios
+
+
+@pytest.mark.parametrize("geom,n,n_internal", [("strip", 65, 128), ("semicircle", 1000, 1024),
+                                               ("archimedean_spiral", 2049, 4096)])
+def test_any_size_matches_oracle(geom, n, n_internal):
+    """N that is not n0 2^V: the leaves are the pieces of the bisection with
+    first halves ceil(m/2) (the oracle's leaf partition, Algorithms 3 and 4),
+    which the library pads to n0 2^V with decoupled unknowns.  2049 splits
+    into leaves at two depths (pieces of 64 stop one level above pieces of 65);
+    65 is the smallest N.  Operator and both preconditioners, forward and
+    adjoint, against the dense oracle at the ID tolerance."""
+    c = getattr(inputs, geom)(n)
+    rho, w = efie.segments(c.xy, c.node_off)
+    A = efie.dense_A(rho, w, KAPPA)
+    x = inputs.random_complex(n, 43)
+    for prec in ("block", "paper"):
+        p = _plan(c, prec=prec)
+        assert p.stats["n"] == n and p.stats["n_internal"] == n_internal
+        for adj in (False, True):
+            Ae = A.conj().T if adj else A
+            assert np.linalg.norm(p.apply(x, adjoint=adj) - Ae @ x) / np.linalg.norm(Ae @ x) < 1e-6
+            ref = (efie.precond_block_apply(A, x, 64, adjoint=adj) if prec == "block"
+                   else efie.precond_paper_apply(A, x, adjoint=adj))
+            assert np.linalg.norm(p.precond(x, adjoint=adj) - ref) / np.linalg.norm(ref) < 2e-6, (prec, adj)
+
+
+def test_any_size_entries_and_impedance():
+    """Entries are addressed by the caller's indices at padded N, and the
+    impedance is taken in the caller's order."""
+    n = 1500
+    c = inputs.semicircle(n)
+    z = inputs.impedance(n, 5)
+    rho, w = efie.segments(c.xy, c.node_off)
+    p = _plan(c, z=z)
+    rows = np.array([0, 1, 749, 750, 1499])
+    cols = np.arange(0, n, 37)
+    ref = efie.entries(rows, cols, rho, w, KAPPA, z=z)
+    assert np.max(np.abs(p.entries(rows, cols) - ref) / np.abs(ref)) < 1e-13
+    A = efie.dense_A(rho, w, KAPPA, z=z)
+    x = inputs.random_complex(n, 44)
+    assert np.linalg.norm(p.apply(x) - A @ x) / np.linalg.norm(A @ x) < 1e-6
