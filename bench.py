@@ -318,7 +318,7 @@ def seconds_per_rhs(geometry, n, R, m, method):
     complex128 solve on the same geometry, both to relres <= 1e-6."""
     import torch
 
-    from paper_1901_11371_amd import inputs
+    from paper_1901_11371_amd import autotune, inputs
     from paper_1901_11371_amd.hbf import Context
     dev = torch.device("cuda", 0)
     curves = inputs.semicircle(n) if geometry == "semicircle" else inputs.archimedean_spiral(n)
@@ -328,9 +328,10 @@ def seconds_per_rhs(geometry, n, R, m, method):
     t0 = time.time()
     ctx = Context(curves, inputs.KAPPA, 64, 1e-6, dtype="c64", max_nrhs=R, restart=m, cache_plan=True)
     log(f"[bench] {geometry} N={n} complex64 context built in {time.time()-t0:.1f}s")
+    tuned_b = autotune.apply(ctx, R) or {"params": autotune.autotune(ctx, nrhs=R, reps=2)}
+    log(f"[bench] {geometry} batched parameters: {tuned_b['params']}")
     kw = dict(tol=1e-6, max_iters=max_iters, method=method)
-    if geometry == "semicircle":
-        ctx.solve(B, **kw)   # warm-up (graph capture)
+    ctx.solve(B, **dict(kw, max_iters=4))   # warm-up: captures the step and sweep graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     X, infos, _ = ctx.solve(B, **kw)
@@ -343,9 +344,10 @@ def seconds_per_rhs(geometry, n, R, m, method):
     t0 = time.time()
     ctx128 = Context(curves, inputs.KAPPA, 64, 1e-6, dtype="c128", max_nrhs=1, restart=m, cache_plan=True)
     log(f"[bench] {geometry} complex128 context built in {time.time()-t0:.1f}s (host plan reused)")
+    tuned_p = autotune.apply(ctx128, 1) or {"params": autotune.autotune(ctx128, nrhs=1, reps=2)}
+    log(f"[bench] {geometry} plain parameters: {tuned_p['params']}")
     b0 = B[0].contiguous()
-    if geometry == "semicircle":
-        ctx128.solve(b0, **kw)
+    ctx128.solve(b0, **dict(kw, max_iters=4))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x128, info128, _ = ctx128.solve(b0, **kw)
@@ -361,6 +363,7 @@ def seconds_per_rhs(geometry, n, R, m, method):
            "batched_converged": all(i["converged"] for i in infos),
            "plain_iters": info128[0]["iters"], "plain_relres": info128[0]["relres"],
            "plain_converged": info128[0]["converged"],
+           "batched_params": tuned_b["params"], "plain_params": tuned_p["params"],
            "batched_c64_vs_c128_solution_rel_diff": diff}
     log(f"[bench] s/RHS {geometry}: batched c64 {t_batched/R*1e3:.2f} ms, plain c128 {t_plain*1e3:.1f} ms, "
         f"iterations {out['batched_iters_max']} / {out['plain_iters']}, solution diff {diff:.2e}")

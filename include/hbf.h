@@ -97,7 +97,10 @@ typedef enum { HBF_GMRES = 0, HBF_TFQMR = 1 } hbf_method;
 
 typedef struct {
   double tol;          /* relative residual target ||b - A x|| / ||b|| (<= 0: 1e-6) */
-  int32_t restart;     /* GMRES restart length m (<= 0: build-time value; capped by it) */
+  int32_t restart;     /* GMRES restart length m (<= 0: build-time value; capped by it).  TFQMR
+                          with complex64 inner vectors: the longest inner cycle (<= 0: 250), after
+                          which the FP64 residual restarts it (the FP32 recurrence residual drifts
+                          from the true residual over long cycles) */
   int32_t max_iters;   /* total inner GMRES iterations per solve (<= 0: 500) */
   int32_t max_refine;  /* outer refinement steps (<= 0: 10) */
   int32_t mixed;       /* 1: inner GMRES in complex64 with FP32 factors and FP64 Arnoldi,
@@ -106,7 +109,7 @@ typedef struct {
   double inner_tol;    /* relative tolerance of each inner cycle (<= 0: 1e-4 when mixed) */
   int32_t method;      /* hbf_method: restarted GMRES(m) (default) or TFQMR (the paper's solver,
                           Sec. 4; no Krylov basis, two matvecs and preconditioner applications per
-                          iteration, `restart` unused) */
+                          iteration) */
 } hbf_solve_opts;
 
 typedef struct {

@@ -273,6 +273,7 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
   const int m = (o.restart > 0) ? std::min(o.restart, c->restart) : c->restart;
   if (m < 1 || m > 255) { set_error(std::string(name) + ": restart must be in [1, 255]"); return HBF_EINVAL; }
   const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
+  const int tq_cycle = o.restart > 0 ? o.restart : 250;
   const int max_refine = o.max_refine > 0 ? o.max_refine : 10;
   const bool inner128 = c->dtype == HBF_C128;
   const bool mixed = !inner128 && o.mixed;
@@ -351,7 +352,11 @@ hbf_status solve_impl(hbf_ctx* c, const void* b, void* x, int32_t nrhs, hbf_dtyp
       if (all) { converged = true; break; }
       if (total >= max_iters || refine >= max_refine + max_iters / m) break;
       chk(hipMemcpyAsync(S.L.target, tgt.data(), R * sizeof(double), hipMemcpyHostToDevice, s), "copy");
-      const int limit = max_iters - total;
+      int limit = max_iters - total;
+      // complex64 TFQMR: its recurrence residual drifts from the true one
+      // over long cycles (FP32 vectors), so a cycle ends after tq_cycle
+      // iterations and the FP64 residual restarts it
+      if (tfqmr && !inner128) limit = std::min(limit, tq_cycle);
       int steps = 0;
       if (!tfqmr) {
         // ---- one GMRES(m) cycle on A d = r ----

@@ -131,6 +131,27 @@ def test_spiral_mixed_c64_vs_dense_lu(torch, spiral4k, method):
     ctx.close()
 
 
+def test_spiral_64_rhs_c64_tfqmr_cycles(torch, spiral4k):
+    """64 plane waves on the N = 4096 spiral with complex64 factors on the
+    matrix cores, TFQMR with the default complex64 cycle length (250): every
+    RHS reaches relres 1e-6 (one unbroken complex64 cycle drifted to a
+    recurrence residual far below the true one and stalled at 4e-3), and
+    two of the solutions agree with dense LU to the spiral's amplification of
+    the ID tolerance."""
+    c, A = spiral4k
+    _say("[solve] spiral N=4096 c64 64 RHS tfqmr")
+    B = inputs.plane_wave_rhs(c, inputs.uniform_angles(64))
+    ctx = _ctx(c, "c64", max_nrhs=64)
+    X, info, st = ctx.solve(torch.tensor(B, device="cuda"), tol=1e-6, max_iters=3000, method="tfqmr")
+    _say(f"  iters max {max(i['iters'] for i in info)} refine {info[0]['refinements']} "
+         f"relres max {max(i['relres'] for i in info):.2e}")
+    assert st == 0 and all(i["converged"] and i["relres"] <= 1e-6 for i in info)
+    X = X.cpu().numpy()
+    for r in (0, 37):
+        assert _rel(X[r], efie.lu_solve(A, B[r])) < 1e-4
+    ctx.close()
+
+
 def test_spiral_iteration_counts_match_oracle(torch, golden_dir):
     """Complex128 GMRES(255) and TFQMR on the N = 4096 spiral take as many
     iterations as the CPU oracle's full GMRES and TFQMR on the dense system
