@@ -62,6 +62,8 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_steps);
   dfree(c->d_punits);
   dfree(c->d_lunits);
+  dfree(c->d_lwaves);
+  c->d_lwaves = nullptr;
   dfree(c->d_arena);
   dfree(c->d_vin);
   dfree(c->d_vout);
@@ -333,7 +335,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
     a.perm = c->d_perm;
     a.buf[BUF_X] = X;
     a.buf[BUF_Y] = Y;
-    a.buf[BUF_ARENA] = c->d_arena;
+    a.buf[BUF_ARENA] = ar;
     a.first = l.first;
     a.direct = l.direct;
     a.R = R;
@@ -349,6 +351,20 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.src_cap = 0;
       a.ch = 0;
       const hipError_t e = launch_stage_mfma_c64(a, l.count, sweep ? c->sweep_mfma_tiles : c->mfma_tiles, adj, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    if (R == 1 && !sweep && !adj && c->lane_units && l.lw_count > 0) {
+      a.rc = 1;
+      a.nchunks = 1;
+      a.acc = l.out_leaf;
+      a.alpha_re = alpha_re;
+      a.alpha_im = alpha_im;
+      const int32_t* wf = c->d_lwaves + l.lw_first;
+      hipError_t e;
+      if (c->dtype == HBF_C128) e = launch_lanes_c128(a, wf, l.lw_count, s);
+      else if (vec_c128) e = launch_lanes_c64_hi(a, wf, l.lw_count, s);
+      else e = launch_lanes_c64(a, wf, l.lw_count, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -625,6 +641,28 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       dmalloc(&c->d_lunits, std::max<size_t>(lu.size(), 1) * sizeof(Unit), "units");
       if (!lu.empty())
         hip_check(hipMemcpy(c->d_lunits, lu.data(), lu.size() * sizeof(Unit), hipMemcpyHostToDevice), "units");
+      // Wave table of the forward launches of single units: consecutive units
+      // whose outputs fill at most 64 lanes (a larger unit takes a wave alone).
+      std::vector<int32_t> lw;
+      for (Launch& l : c->mv_fwd) {
+        if (!l.direct || l.count <= 0) continue;
+        const std::vector<Unit>& us = l.ucopy ? lu : P.units;
+        l.lw_first = static_cast<int32_t>(lw.size());
+        int fill = 0;
+        for (int32_t u = l.first; u < l.first + l.count; ++u) {
+          const int n = us[u].out_len[0] + us[u].out_len[1];
+          if (u == l.first || fill + n > 64) {
+            lw.push_back(u);
+            fill = 0;
+          }
+          fill += n;
+        }
+        lw.push_back(l.first + l.count);
+        l.lw_count = static_cast<int32_t>(lw.size()) - 1 - l.lw_first;
+      }
+      dmalloc(&c->d_lwaves, std::max<size_t>(lw.size(), 1) * sizeof(int32_t), "units");
+      if (!lw.empty())
+        hip_check(hipMemcpy(c->d_lwaves, lw.data(), lw.size() * sizeof(int32_t), hipMemcpyHostToDevice), "units");
     }
     progress("factors uploaded");
     rebuild_sweeps(c.get(), c->S.prog_levels);
@@ -817,6 +855,11 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     } catch (const std::exception& e) {
       return fail(HBF_ENOMEM, std::string("hbf_tune: ") + e.what());
     }
+    return HBF_OK;
+  }
+  if (k == "lane_units") {
+    if (value != 0 && value != 1) return fail(HBF_EINVAL, "hbf_tune: lane_units must be 0 or 1");
+    c->lane_units = value != 0;
     return HBF_OK;
   }
   if (k == "mv_direct") {

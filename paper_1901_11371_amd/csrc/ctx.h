@@ -50,6 +50,8 @@ struct hbf_ctx {
   int32_t* d_steps = nullptr;  // program steps of the sweeps
   hbf::Unit* d_punits = nullptr;  // unit copies of the programs with LDS-resident vectors
   hbf::Unit* d_lunits = nullptr;  // launch-order unit copies of the direct matvec launches
+  int32_t* d_lwaves = nullptr;    // wave table of the lane-per-output matvec launches
+  bool lane_units = true;      // one-RHS forward matvec launches of single units: one lane per output
   std::vector<hbf::Launch> mv_fwd, mv_adj;  // matvec schedules as launched (mv_direct)
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
   void* d_vin = nullptr;       // internal-layout vectors, n x max_nrhs x 16 bytes each

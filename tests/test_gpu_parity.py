@@ -142,6 +142,8 @@ TUNINGS = [
     {"prog_lds": 0, "prog_levels": 6},
     {"mv_direct": 0},
     {"mv_direct": 0, "lane_split": 0},
+    {"lane_units": 0},
+    {"lane_units": 0, "lane_split": 0},
     {"r1_max_blocks": 2048},
     {"r1_max_blocks": 3, "sweep_pipe_max_r": 8},
     {"mfma_min_r": 1},
