@@ -49,7 +49,8 @@ def log(*a):
 
 # the sources that decide what the single-RHS matvec reads and writes: the
 # factor layout, the launch schedule and the stage kernel
-MATVEC_SOURCES = ("hbf_internal.h", "kernels.h", "plan.cpp", "ctx.cpp", "stage_pipe.hip")
+MATVEC_SOURCES = ("hbf_internal.h", "kernels.h", "lane_unit.h", "plan.cpp", "ctx.cpp", "stage_pipe.hip",
+                  "stage_lanes.hip")
 
 
 def host_cores():

@@ -234,6 +234,8 @@ hbf_status hbf_impedance_grad(hbf_ctx* ctx, const void* lam, const void* x, int3
  *                   their unit descriptors in launch order (default 1),
  *   "lane_units"    1 = with one RHS, those forward stages give each lane one
  *                   output row of a run of units (default 1; needs mv_direct),
+ *   "lane_max_entries"  ... for stages whose units average at most this many
+ *                   matrix entries (default 640),
  *   "use_graphs"    1 = replay the preconditioner sweeps and the solvers' steps
  *                   from HIP graphs,
  *   "mfma"          1 = complex64 stage launches with nrhs >= mfma_min_r run

@@ -63,7 +63,9 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_punits);
   dfree(c->d_lunits);
   dfree(c->d_lwaves);
+  dfree(c->d_lmap);
   c->d_lwaves = nullptr;
+  c->d_lmap = nullptr;
   dfree(c->d_arena);
   dfree(c->d_vin);
   dfree(c->d_vout);
@@ -354,17 +356,21 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       if (e != hipSuccess) return e;
       continue;
     }
-    if (R == 1 && !sweep && !adj && c->lane_units && l.lw_count > 0) {
+    // launches of big units (the leaf transfers of 64-row sources, the middle
+    // couplings) stay with the wave-per-unit kernels, which stream a unit's
+    // matrix with whole-wave loads
+    if (R == 1 && !sweep && !adj && c->lane_units && l.lw_count > 0 && l.lw_mean <= c->lane_max_entries) {
       a.rc = 1;
       a.nchunks = 1;
       a.acc = l.out_leaf;
       a.alpha_re = alpha_re;
       a.alpha_im = alpha_im;
       const int32_t* wf = c->d_lwaves + l.lw_first;
+      const uint16_t* lmap = c->d_lmap + static_cast<int64_t>(l.lw_first) * 64;
       hipError_t e;
-      if (c->dtype == HBF_C128) e = launch_lanes_c128(a, wf, l.lw_count, s);
-      else if (vec_c128) e = launch_lanes_c64_hi(a, wf, l.lw_count, s);
-      else e = launch_lanes_c64(a, wf, l.lw_count, s);
+      if (c->dtype == HBF_C128) e = launch_lanes_c128(a, wf, lmap, l.lw_count, s);
+      else if (vec_c128) e = launch_lanes_c64_hi(a, wf, lmap, l.lw_count, s);
+      else e = launch_lanes_c64(a, wf, lmap, l.lw_count, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -641,28 +647,51 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       dmalloc(&c->d_lunits, std::max<size_t>(lu.size(), 1) * sizeof(Unit), "units");
       if (!lu.empty())
         hip_check(hipMemcpy(c->d_lunits, lu.data(), lu.size() * sizeof(Unit), hipMemcpyHostToDevice), "units");
-      // Wave table of the forward launches of single units: consecutive units
-      // whose outputs fill at most 64 lanes (a larger unit takes a wave alone).
+      // Lane tables of the forward launches of single units: a wave takes a
+      // run of consecutive units whose outputs fill at most 64 lanes, or a
+      // 64-row slice of a larger unit; lane l of wave w computes the output
+      // lmap[64 w + l] = (unit - wfirst[w]) << 8 | row (0xffff: idle).
       std::vector<int32_t> lw;
+      std::vector<uint16_t> lm;
       for (Launch& l : c->mv_fwd) {
         if (!l.direct || l.count <= 0) continue;
         const std::vector<Unit>& us = l.ucopy ? lu : P.units;
+        int64_t ent = 0;
+        for (int32_t u = l.first; u < l.first + l.count; ++u) ent += us[u].mat_len;
+        l.lw_mean = static_cast<int32_t>(ent / l.count);
         l.lw_first = static_cast<int32_t>(lw.size());
+        int32_t run = -1;  // first unit of the open run (-1: none)
         int fill = 0;
         for (int32_t u = l.first; u < l.first + l.count; ++u) {
           const int n = us[u].out_len[0] + us[u].out_len[1];
-          if (u == l.first || fill + n > 64) {
-            lw.push_back(u);
-            fill = 0;
+          if (n > 64) {
+            for (int o0 = 0; o0 < n; o0 += 64) {
+              lw.push_back(u);
+              lm.resize(lw.size() * 64, 0xffff);
+              for (int o = o0; o < std::min(n, o0 + 64); ++o)
+                lm[(lw.size() - 1) * 64 + (o - o0)] = static_cast<uint16_t>(o);
+            }
+            run = -1;
+            continue;
           }
+          if (run < 0 || fill + n > 64 || u - run > 255) {
+            run = u;
+            fill = 0;
+            lw.push_back(u);
+            lm.resize(lw.size() * 64, 0xffff);
+          }
+          for (int o = 0; o < n; ++o)
+            lm[(lw.size() - 1) * 64 + fill + o] = static_cast<uint16_t>(((u - run) << 8) | o);
           fill += n;
         }
-        lw.push_back(l.first + l.count);
-        l.lw_count = static_cast<int32_t>(lw.size()) - 1 - l.lw_first;
+        l.lw_count = static_cast<int32_t>(lw.size()) - l.lw_first;
       }
       dmalloc(&c->d_lwaves, std::max<size_t>(lw.size(), 1) * sizeof(int32_t), "units");
-      if (!lw.empty())
+      dmalloc(&c->d_lmap, std::max<size_t>(lm.size(), 1) * sizeof(uint16_t), "units");
+      if (!lw.empty()) {
         hip_check(hipMemcpy(c->d_lwaves, lw.data(), lw.size() * sizeof(int32_t), hipMemcpyHostToDevice), "units");
+        hip_check(hipMemcpy(c->d_lmap, lm.data(), lm.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "units");
+      }
     }
     progress("factors uploaded");
     rebuild_sweeps(c.get(), c->S.prog_levels);
@@ -857,14 +886,19 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     }
     return HBF_OK;
   }
-  if (k == "lane_units") {
-    if (value != 0 && value != 1) return fail(HBF_EINVAL, "hbf_tune: lane_units must be 0 or 1");
-    c->lane_units = value != 0;
+  if (k == "lane_max_entries") {
+    if (value < 0 || value > (1 << 20)) return fail(HBF_EINVAL, "hbf_tune: lane_max_entries out of range");
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    c->lane_max_entries = static_cast<int>(value);
     return HBF_OK;
   }
-  if (k == "mv_direct") {
-    if (value != 0 && value != 1) return fail(HBF_EINVAL, "hbf_tune: mv_direct must be 0 or 1");
-    c->mv_direct = value != 0;
+  if (k == "lane_units" || k == "mv_direct") {
+    if (value != 0 && value != 1) return fail(HBF_EINVAL, "hbf_tune: " + k + " must be 0 or 1");
+    // the solver's captured steps hold the matvec and sweep launches
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    (k == "lane_units" ? c->lane_units : c->mv_direct) = value != 0;
     return HBF_OK;
   }
   if (k == "prog_lds") {

@@ -50,8 +50,10 @@ struct hbf_ctx {
   int32_t* d_steps = nullptr;  // program steps of the sweeps
   hbf::Unit* d_punits = nullptr;  // unit copies of the programs with LDS-resident vectors
   hbf::Unit* d_lunits = nullptr;  // launch-order unit copies of the direct matvec launches
-  int32_t* d_lwaves = nullptr;    // wave table of the lane-per-output matvec launches
+  int32_t* d_lwaves = nullptr;    // lane-per-output matvec launches: first unit of each wave
+  uint16_t* d_lmap = nullptr;     // ... and each lane's unit offset and output row
   bool lane_units = true;      // one-RHS forward matvec launches of single units: one lane per output
+  int lane_max_entries = 640;  // ... for launches whose units average at most this many matrix entries
   std::vector<hbf::Launch> mv_fwd, mv_adj;  // matvec schedules as launched (mv_direct)
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
   void* d_vin = nullptr;       // internal-layout vectors, n x max_nrhs x 16 bytes each

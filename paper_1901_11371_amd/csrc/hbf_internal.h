@@ -81,10 +81,11 @@ struct Launch {
   int32_t force_fwd = 0;  // 1: apply the units in forward mode even in an adjoint schedule
   int32_t single = 1;     // 1: every group is one unit (no accumulation across units)
   int32_t ucopy = 0;      // 1: direct over the device's launch-order unit copies
-  // one-RHS forward launches of single units: the launch's runs of units per
-  // wave for the lane-per-output kernel (entries [lw_first, lw_first +
-  // lw_count] of the context's wave table; lw_count = 0: none)
+  // one-RHS forward launches of single units: the launch's waves of the
+  // lane-per-output kernel (entries [lw_first, lw_first + lw_count) of the
+  // context's wave tables; lw_count = 0: none)
   int32_t lw_first = 0, lw_count = 0;
+  int32_t lw_mean = 0;    // mean matrix entries per unit of the launch
   // program kept in LDS (lv_rows > 0): its steps index the rewritten unit
   // copies of Sweeps::punits, whose vector segments are LDS rows: the
   // program's rows [prow0, prow0 + prows) of X at [0, prows), of Y at

@@ -68,11 +68,15 @@ hipError_t launch_prog_pipe_c128(const StageArgs& a, const int32_t* steps, int s
 // complex GEMMs on FP32 matrix cores (stage_mfma.hip).
 // tiles: 16-RHS column tiles per wave (1, 2 or 4)
 hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, bool adjoint, hipStream_t s);
-// One right-hand side, forward, launches of single units: one lane per output,
-// a wave over the run of units wfirst[w] .. wfirst[w + 1] (stage_lanes.hip).
-hipError_t launch_lanes_c64(const StageArgs& a, const int32_t* wfirst, int nwaves, hipStream_t s);
-hipError_t launch_lanes_c64_hi(const StageArgs& a, const int32_t* wfirst, int nwaves, hipStream_t s);
-hipError_t launch_lanes_c128(const StageArgs& a, const int32_t* wfirst, int nwaves, hipStream_t s);
+// One right-hand side, forward, launches of single units: one lane per output;
+// wave w covers units from wfirst[w] on, lane l of it the output named by
+// lmap[64 w + l] ((unit offset) << 8 | row; 0xffff idle) (stage_lanes.hip).
+hipError_t launch_lanes_c64(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, int nwaves,
+                            hipStream_t s);
+hipError_t launch_lanes_c64_hi(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, int nwaves,
+                               hipStream_t s);
+hipError_t launch_lanes_c128(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, int nwaves,
+                             hipStream_t s);
 // Wave-per-group variant (4 groups per workgroup, wave_lds bytes of LDS each).
 hipError_t launch_stage_wave_c64(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
 hipError_t launch_stage_wave_c128(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);

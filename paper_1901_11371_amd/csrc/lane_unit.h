@@ -1,0 +1,87 @@
+// One output row of one unit of the factor chain, applied forward to one
+// right-hand side by a single lane (the lane-per-output kernels of the matvec
+// stages and of the sweep programs).  src(s) returns source entry s of the
+// unit (0 <= s < n_src) in the accumulation type A.
+//   GATHER  (column-ID transfer):  out_o[i] = src[perm_o[i]]
+//           + sum_t T_o(i, t) src[perm_o[k_o + t]]; T_o is column-major, so at
+//           each t the lanes of one ID read consecutive entries;
+//   SCATTER (row-ID transfer):     out[p] = sum over the two IDs of in_o[q] if
+//           q = invperm_o[p] < k_o, else sum_j T_o(j, q - k_o) in_o[j];
+//   DENSE:  out[o] = sum_t M(o, t) src[t], column-major.
+#pragma once
+
+#include "kernels.h"
+
+namespace hbf {
+namespace lanes {
+
+template <class T>
+__device__ __forceinline__ void mac(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+template <class A, class S>
+__device__ __forceinline__ cx<A> widen(cx<S> v) {
+  return cx<A>{static_cast<A>(v.x), static_cast<A>(v.y)};
+}
+
+template <class F, class A, class SrcF>
+__device__ __forceinline__ cx<A> unit_output(const Unit& U, int o, const cx<F>* fac_all, const uint8_t* perm_all,
+                                             const SrcF& src) {
+  const int type = U.type;
+  const int k0 = U.k[0], k1 = U.k[1];
+  const int f_in = U.in_len[0] + U.in_len[1];
+  const int f_out = U.out_len[0] + U.out_len[1];
+  const cx<F>* fac = fac_all + U.mat;
+  const uint8_t* pp = perm_all + U.perm;
+  cx<A> val{0, 0};
+  if (type == UNIT_GATHER) {
+    const int id = o < k0 ? 0 : 1;
+    const int i = id ? o - k0 : o;
+    const int k = id ? k1 : k0;
+    const int r = f_in - k;
+    const cx<F>* T = fac + (id ? k0 * (f_in - k0) : 0) + i;
+    const uint8_t* pm = pp + id * f_in;
+    val = src(pm[i]);
+#pragma unroll 4
+    for (int t = 0; t < r; ++t) mac(val, widen<A>(T[t * k]), src(pm[k + t]));
+  } else if (type == UNIT_SCATTER) {
+#pragma unroll
+    for (int id = 0; id < 2; ++id) {
+      const int k = id ? k1 : k0;
+      const int r = f_out - k;
+      const int q = pp[id * f_out + o];
+      const int sbase = id ? k0 : 0;
+      if (q < k) {
+        const cx<A> v = src(sbase + q);
+        val.x += v.x;
+        val.y += v.y;
+      } else {
+        const cx<F>* T = fac + (id ? k0 * (f_out - k0) : 0) + (q - k);
+#pragma unroll 4
+        for (int j = 0; j < k; ++j) mac(val, widen<A>(T[j * r]), src(sbase + j));
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int t = 0; t < f_in; ++t) mac(val, widen<A>(fac[t * f_out + o]), src(t));
+  }
+  return val;
+}
+
+// dst = val (acc == 0) or dst + alpha val
+template <class V, class A>
+__device__ __forceinline__ void store(V* dp, cx<A> val, int acc, double alpha_re, double alpha_im) {
+  if (acc) {
+    const A are = static_cast<A>(alpha_re), aim = static_cast<A>(alpha_im);
+    const cx<A> cu = widen<A>(*dp);
+    val = cx<A>{cu.x + are * val.x - aim * val.y, cu.y + are * val.y + aim * val.x};
+  }
+  using VT = decltype(dp->x);
+  *dp = V{static_cast<VT>(val.x), static_cast<VT>(val.y)};
+}
+
+}  // namespace lanes
+}  // namespace hbf

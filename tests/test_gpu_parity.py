@@ -144,6 +144,9 @@ TUNINGS = [
     {"mv_direct": 0, "lane_split": 0},
     {"lane_units": 0},
     {"lane_units": 0, "lane_split": 0},
+    {"lane_max_entries": 128},
+    {"lane_max_entries": 1 << 20},
+    {"prog_levels": 7},
     {"r1_max_blocks": 2048},
     {"r1_max_blocks": 3, "sweep_pipe_max_r": 8},
     {"mfma_min_r": 1},
