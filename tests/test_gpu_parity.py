@@ -198,8 +198,22 @@ def test_execution_parameters_keep_results(torch, spiral, tuning_refs, tuning):
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def refs64(spiral):
+    """Oracle products of the 64 seeded RHS of the matrix-core tests (A X,
+    A^H X, and P^-1, P^-H of the first 16), computed once: the oracle's
+    block substitutions take all 16 columns in one dense solve each."""
+    c, A = spiral
+    X = inputs.random_complex((64, 4096), 37)
+    out = {"X": X}
+    for adj in (False, True):
+        out[("mv", adj)] = X @ (A.conj() if adj else A.T)
+        out[("pc", adj)] = efie.precond_block_apply(A, X[:16].T, 64, adjoint=adj).T
+    return out
+
+
 @pytest.mark.parametrize("mfma,tiles", [(1, 4), (1, 2), (1, 1), (0, 4)])
-def test_64_rhs_on_matrix_cores(torch, spiral, mfma, tiles):
+def test_64_rhs_on_matrix_cores(torch, spiral, refs64, mfma, tiles):
     """64 right-hand sides (the batched launch shape): matvec and
     preconditioner, forward and adjoint, with the matrix-core stage launches
     (and without them), against the oracle, with relative L2 and worst-row
@@ -209,17 +223,17 @@ def test_64_rhs_on_matrix_cores(torch, spiral, mfma, tiles):
     ctx = _ctx(c, "c64", max_nrhs=64)
     ctx.tune("mfma", mfma)
     ctx.tune("mfma_tiles", tiles)
-    X = inputs.random_complex((64, 4096), 37)
+    X = refs64["X"]
     Xt = torch.tensor(X, dtype=torch.complex64, device="cuda")
     for adj in (False, True):
         Y = ctx.matvec(Xt, adjoint=adj).cpu().numpy()
-        ref = X @ (A.conj() if adj else A.T)
+        ref = refs64[("mv", adj)]
         err, rowerr = _rel(Y, ref), _rowmax(Y, ref)
         y1 = ctx.matvec(Xt[40].contiguous(), adjoint=adj).cpu().numpy()
         _say(f"  matvec adjoint={adj} rel err {err:.3e} worst row {rowerr:.3e} col40 vs single {_rel(Y[40], y1):.2e}")
         assert err < 5e-6 and rowerr < 2e-5 and _rel(Y[40], y1) < 1e-5
         Z = ctx.precond(Xt[:16].contiguous(), adjoint=adj).cpu().numpy()
-        refz = np.stack([efie.precond_block_apply(A, X[i], 64, adjoint=adj) for i in range(16)])
+        refz = refs64[("pc", adj)]
         errz, rowz = _rel(Z, refz), _rowmax(Z, refz)
         _say(f"  precond (16 rhs) adjoint={adj} rel err {errz:.3e} worst row {rowz:.3e}")
         assert errz < 5e-5 and rowz < 2e-4
