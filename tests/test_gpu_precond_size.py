@@ -81,13 +81,28 @@ def test_precond_spiral_2p14_vs_stored_oracle(torch, golden14, prec, dtype):
     ctx.close()
 
 
-def test_precond_parabola_2p16_vs_host_executor(torch):
+# the execution parameters the benchmark's autotuner picks for 64 RHS at N = 2^20
+TUNED_64 = {"prog_levels": 5, "pipe_max_r": 4, "sweep_pipe_max_r": 4, "wave_units": 1, "sweep_rc1": 0, "mfma": 1,
+            "mfma_min_r": 1, "mfma_tiles": 4, "sweep_mfma_tiles": 1}
+
+
+@pytest.mark.parametrize("case", ["parabola-2p16", "spiral-2p18-tuned"])
+def test_precond_vs_host_executor(torch, case):
+    """Device sweeps against the host FP64 executor of the same
+    factorisation (itself pinned against the dense oracle at N = 4096):
+    the parabola at 2^16 with the default execution parameters, and the
+    spiral at 2^18 with the benchmark's tuned ones (subtree programs of 32
+    leaves, matrix-core sweep stages), 1 and 64 RHS, forward and adjoint."""
     from paper_1901_11371_amd.hbf import Context, HostPlan
-    n = 1 << 16
-    c = inputs.parabola(n)
-    _say("[precond 2^16] parabola c64, device sweeps vs host FP64 executor")
+    geom, size = case.split("-")[:2]
+    n = 1 << int(size[2:])
+    c = inputs.parabola(n) if geom == "parabola" else inputs.archimedean_spiral(n)
+    _say(f"[precond {case}] c64, device sweeps vs host FP64 executor")
     plan = HostPlan(c, KAPPA, 64, 1e-6, dtype="c64")
     ctx = Context(c, KAPPA, 64, 1e-6, dtype="c64", max_nrhs=64)
+    if case.endswith("tuned"):
+        for k, v in TUNED_64.items():
+            ctx.tune(k, v)
     X = inputs.random_complex((64, n), 91)
     for adj in (False, True):
         ref = plan.precond(X[:4], adjoint=adj)
