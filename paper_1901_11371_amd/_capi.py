@@ -21,7 +21,8 @@ class Curve(C.Structure):
 class BuildOpts(C.Structure):
     _fields_ = [("dtype", C.c_int), ("prec", C.c_int), ("eta0", C.c_double), ("z", C.POINTER(C.c_double)),
                 ("max_nrhs", C.c_int32), ("restart", C.c_int32), ("device", C.c_int32), ("nthreads", C.c_int32),
-                ("cache_plan", C.c_int32), ("superleaf", C.c_int32), ("verbose", C.c_int32)]
+                ("cache_plan", C.c_int32), ("superleaf", C.c_int32), ("verbose", C.c_int32),
+                ("host_entries", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -11,7 +11,8 @@ OUT_DIR = os.path.join(HERE, "_lib")
 OUT = os.path.join(OUT_DIR, "libhbf.so")
 
 HOST_SOURCES = ["hankel.cpp", "plan.cpp", "schedule.cpp", "ctx.cpp", "solver.cpp"]
-DEVICE_SOURCES = ["stage.hip", "stage_pipe.hip", "stage_mfma.hip", "stage_lanes.hip", "gmres.hip", "noalloc.hip"]
+DEVICE_SOURCES = ["stage.hip", "stage_pipe.hip", "stage_mfma.hip", "stage_lanes.hip", "gmres.hip", "noalloc.hip",
+                  "entries.hip"]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fcx-limited-range",
              # packed FP32 instructions stay disabled (see the build notes)

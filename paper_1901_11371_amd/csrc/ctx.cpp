@@ -566,7 +566,10 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
         }
       }
       if (!hit) {
-        build_plan(c->P, curve, kappa, leaf, tol, opts);
+        std::unique_ptr<EntryEval> ev;
+        if (!(opts && opts->host_entries)) ev = make_device_entry_eval(c->device);
+        build_plan(c->P, curve, kappa, leaf, tol, opts, ev.get());
+        progress("host plan built");
         if (opts && opts->cache_plan) {
           std::lock_guard<std::mutex> lk(pc.mu);
           pc.plan = c->P;

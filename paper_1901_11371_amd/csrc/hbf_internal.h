@@ -4,6 +4,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -165,9 +166,35 @@ struct Plan {
   int64_t lib(int64_t i) const { return lib_of.empty() ? i : lib_of[i]; }
 };
 
-// Build the plan (host only).  Throws std::runtime_error on invalid input.
+// A product of index sets whose kernel entries the construction needs:
+// out[c * nrows + a] = swap ? entry(cols[c], rows[a]) : entry(rows[a], cols[c]).
+struct EntryJob {
+  const int32_t* rows;
+  int32_t nrows;
+  const int32_t* cols;
+  int32_t ncols;
+  int32_t swap;
+  cplx* out;
+};
+
+// Batched evaluation of kernel entries for the construction: prepare() once
+// the plan's geometry, impedance and padding are final, then any number of
+// eval() calls (each blocking until its outputs are written).
+class EntryEval {
+ public:
+  virtual ~EntryEval() = default;
+  virtual void prepare(const Plan& P) = 0;
+  virtual void eval(const std::vector<EntryJob>& jobs) = 0;
+};
+
+// The device evaluator (entries.hip): FP64 entries on the given HIP device.
+std::unique_ptr<EntryEval> make_device_entry_eval(int device);
+
+// Build the plan.  Throws std::runtime_error on invalid input.  With `eval`,
+// the kernel entries of the ID samples and probes and of the dense blocks are
+// evaluated through it in batches; the IDs themselves run on the host.
 void build_plan(Plan& p, const hbf_curve* curve, double kappa, int leaf, double tol,
-                const hbf_build_opts* opts);
+                const hbf_build_opts* opts, EntryEval* eval = nullptr);
 
 // Host FP64 evaluation of the plan: y = A x or A^H x for nrhs vectors
 // (x, y are (nrhs, N) complex128).

@@ -206,8 +206,58 @@ void column_id(std::vector<cplx>& M, int s, int n, double eps, int kmax, IdRec& 
 // on a pseudo-random probe of other partner indices and the sample grows
 // until the probe residual is at the tolerance (or the sample is the whole
 // partner set).
+// The first sample and the first probe of compute_id for the same arguments
+// (their index sets, in the same order), with room for their matrices, so a
+// batch of IDs can have those matrices evaluated together beforehand.
+struct IdPrefetch {
+  std::vector<int32_t> samp, probe;
+  std::vector<cplx> Ms, Mp;
+  bool ready = false;
+};
+
+uint64_t id_seed(int64_t plo, const std::vector<int32_t>& cand) {
+  return 0x9E3779B97F4A7C15ull ^ (static_cast<uint64_t>(plo) * 0xBF58476D1CE4E5B9ull) ^
+         (static_cast<uint64_t>(cand[0]) << 20) ^ static_cast<uint64_t>(cand.size());
+}
+
+uint64_t id_rnd(uint64_t& seed) {
+  seed ^= seed >> 30; seed *= 0xBF58476D1CE4E5B9ull;
+  seed ^= seed >> 27; seed *= 0x94D049BB133111EBull;
+  seed ^= seed >> 31;
+  return seed;
+}
+
+constexpr int kProbe = 16;  // partner indices of a probe
+
+void id_first_sets(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, int64_t pn, IdPrefetch& pf) {
+  const int n = static_cast<int>(cand.size());
+  pf.samp.clear();
+  pf.probe.clear();
+  pf.ready = false;
+  std::vector<int32_t> pos;
+  const bool padded = !P.ghost.empty();
+  if (padded) real_indices(P, plo, pn, pos);
+  const int64_t pr = padded ? static_cast<int64_t>(pos.size()) : pn;
+  if (pr == 0) return;
+  auto to_partner = [&](std::vector<int32_t>& v) {
+    if (padded)
+      for (auto& x : v) x = pos[x];
+    else
+      for (auto& x : v) x += static_cast<int32_t>(plo);
+  };
+  const int s = static_cast<int>(std::min<int64_t>(pr, std::max(48, n / 2 + 16)));
+  mock_cheb(0, pr, s, pf.samp);
+  to_partner(pf.samp);
+  uint64_t seed = id_seed(plo, cand);
+  pf.probe.resize(kProbe);
+  for (int a = 0; a < kProbe; ++a) pf.probe[a] = static_cast<int32_t>(id_rnd(seed) % pr);
+  to_partner(pf.probe);
+  pf.Ms.resize(pf.samp.size() * n);
+  pf.Mp.resize(pf.probe.size() * n);
+}
+
 void compute_id(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, int64_t pn,
-                bool partner_is_rows, double eps, IdRec& out) {
+                bool partner_is_rows, double eps, IdRec& out, IdPrefetch* pf = nullptr) {
   const int n = static_cast<int>(cand.size());
   int s = static_cast<int>(std::min<int64_t>(pn, std::max(48, n / 2 + 16)));
   std::vector<int32_t> samp, probe;
@@ -219,13 +269,13 @@ void compute_id(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, in
       for (int a = 0; a < ss; ++a)
         A[static_cast<size_t>(c) * ss + a] = partner_is_rows ? P.entry(pts[a], cand[c]) : P.entry(cand[c], pts[a]);
   };
-  uint64_t seed = 0x9E3779B97F4A7C15ull ^ (static_cast<uint64_t>(plo) * 0xBF58476D1CE4E5B9ull) ^
-                  (static_cast<uint64_t>(cand[0]) << 20) ^ static_cast<uint64_t>(n);
-  auto rnd = [&]() {
-    seed ^= seed >> 30; seed *= 0xBF58476D1CE4E5B9ull;
-    seed ^= seed >> 27; seed *= 0x94D049BB133111EBull;
-    seed ^= seed >> 31;
-    return seed;
+  uint64_t seed = id_seed(plo, cand);
+  auto rnd = [&]() { return id_rnd(seed); };
+  // prefetched matrices (same index sets as computed here) replace the host evaluation
+  auto fill_or_take = [&](const std::vector<int32_t>& pts, std::vector<cplx>& A, const std::vector<int32_t>& pre,
+                          std::vector<cplx>& preM) {
+    if (pf && pf->ready && pts == pre && preM.size() == pts.size() * static_cast<size_t>(n)) A.swap(preM);
+    else fill(pts, A);
   };
   // the partner set: its real unknowns, addressed by position pos[0..pr)
   std::vector<int32_t> pos;
@@ -251,7 +301,8 @@ void compute_id(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, in
     mock_cheb(0, pr, s, samp);
     to_partner(samp);
     const int ss = static_cast<int>(samp.size());
-    fill(samp, M);
+    if (pf) fill_or_take(samp, M, pf->samp, pf->Ms);
+    else fill(samp, M);
     column_id(M, ss, n, eps, std::min(n, 127), out);
     if (ss >= pr) break;
     const int need = 2 * out.k + 16;
@@ -260,12 +311,13 @@ void compute_id(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, in
       continue;
     }
     // probe: residual of K(probe, p) - K(probe, q) T relative to K(probe, cand)
-    const int np = 16;
+    const int np = kProbe;
     probe.resize(np);
     for (int a = 0; a < np; ++a) probe[a] = static_cast<int32_t>(rnd() % pr);
     to_partner(probe);
     const int npr = np;
-    fill(probe, Mp);
+    if (pf) fill_or_take(probe, Mp, pf->probe, pf->Mp);
+    else fill(probe, Mp);
     const int k = out.k, r = n - k;
     double rn = 0.0, an = 0.0;
     for (int c = 0; c < n; ++c)
@@ -313,7 +365,10 @@ Unit blank_unit(uint8_t type) {
 // ---------------------------------------------------------------------------
 // IDBF of every off-diagonal block of one H-level (all blocks share L).
 // ---------------------------------------------------------------------------
-void build_level_blocks(Plan& P, int v, double eps, int nthreads) {
+// IDs whose first sample and probe matrices are evaluated in one batch.
+constexpr int64_t kIdBatch = 8192;
+
+void build_level_blocks(Plan& P, int v, double eps, int nthreads, EntryEval* eval) {
   const int64_t N = P.n;
   const int64_t nv = N >> v;           // block size
   const int L = P.V - v;
@@ -351,8 +406,17 @@ void build_level_blocks(Plan& P, int v, double eps, int nthreads) {
   for (int d = 1; d <= D; ++d) {
     Rcur.assign(static_cast<size_t>(nb * nid), IdRec());
     Ccur.assign(static_cast<size_t>(nb * nid), IdRec());
-    const int lvl_r = L - d + 1;  // row level of the row IDs / column level of the column IDs
-    parallel_for(2 * nb * nid, nthreads, [&](int64_t job) {
+    // one job per ID: its candidates (the IDs of the previous level's child
+    // nodes, or the leaf rows/columns) and its partner range
+    struct Job {
+      std::vector<int32_t> cand;
+      int64_t plo = 0, pn = 0;
+      bool partner_rows = false;
+      IdPrefetch pf;
+    };
+    const int64_t njobs = 2 * nb * nid;
+    std::vector<Job> jobs(static_cast<size_t>(njobs));
+    parallel_for(njobs, nthreads, [&](int64_t job) {
       const bool row_side = job < nb * nid;
       const int64_t jj = row_side ? job : job - nb * nid;
       const int64_t b = jj / nid;
@@ -360,36 +424,60 @@ void build_level_blocks(Plan& P, int v, double eps, int nthreads) {
       const BlockInfo& bi = P.blocks[b0 + b];
       const int64_t a = id >> d;                 // node at level L-d+1 on the ID's own side
       const int64_t o = id & ((int64_t(1) << d) - 1);  // partner node at level d
-      std::vector<int32_t> cand;
-      if (row_side) {
-        if (d == 1) {
-          for (int i = 0; i < n0; ++i) cand.push_back(static_cast<int32_t>(bi.row0 + a * n0 + i));
-        } else {
-          const int64_t op = o >> 1;
-          for (int c = 0; c < 2; ++c) {
-            const IdRec& ch = Rprev[b * nid + (((2 * a + c) << (d - 1)) + op)];
-            cand.insert(cand.end(), ch.skel.begin(), ch.skel.end());
-          }
-        }
-        auto pr = leaf_range(o, d);
-        compute_id(P, cand, bi.col0 + pr.first, pr.second, /*partner_is_rows=*/false, eps,
-                   Rcur[b * nid + id]);
+      Job& J = jobs[job];
+      const std::vector<IdRec>& prev = row_side ? Rprev : Cprev;
+      const int64_t own0 = row_side ? bi.row0 : bi.col0;
+      if (d == 1) {
+        for (int i = 0; i < n0; ++i) J.cand.push_back(static_cast<int32_t>(own0 + a * n0 + i));
       } else {
-        if (d == 1) {
-          for (int i = 0; i < n0; ++i) cand.push_back(static_cast<int32_t>(bi.col0 + a * n0 + i));
-        } else {
-          const int64_t op = o >> 1;
-          for (int c = 0; c < 2; ++c) {
-            const IdRec& ch = Cprev[b * nid + (((2 * a + c) << (d - 1)) + op)];
-            cand.insert(cand.end(), ch.skel.begin(), ch.skel.end());
-          }
+        const int64_t op = o >> 1;
+        for (int c = 0; c < 2; ++c) {
+          const IdRec& ch = prev[b * nid + (((2 * a + c) << (d - 1)) + op)];
+          J.cand.insert(J.cand.end(), ch.skel.begin(), ch.skel.end());
         }
-        auto pr = leaf_range(o, d);
-        compute_id(P, cand, bi.row0 + pr.first, pr.second, /*partner_is_rows=*/true, eps,
-                   Ccur[b * nid + id]);
       }
-      (void)lvl_r;
+      auto pr = leaf_range(o, d);
+      J.plo = (row_side ? bi.col0 : bi.row0) + pr.first;
+      J.pn = pr.second;
+      J.partner_rows = !row_side;  // row IDs sample the partner columns, column IDs the partner rows
     });
+    auto run_ids = [&](int64_t j0, int64_t j1, bool pre) {
+      parallel_for(j1 - j0, nthreads, [&](int64_t q) {
+        const int64_t job = j0 + q;
+        const bool row_side = job < nb * nid;
+        const int64_t jj = row_side ? job : job - nb * nid;
+        Job& J = jobs[job];
+        IdRec& out = row_side ? Rcur[jj] : Ccur[jj];
+        compute_id(P, J.cand, J.plo, J.pn, J.partner_rows, eps, out, pre ? &J.pf : nullptr);
+        J.pf = IdPrefetch();
+      });
+    };
+    if (!eval) {
+      run_ids(0, njobs, false);
+    } else {
+      for (int64_t j0 = 0; j0 < njobs; j0 += kIdBatch) {
+        const int64_t j1 = std::min(njobs, j0 + kIdBatch);
+        parallel_for(j1 - j0, nthreads, [&](int64_t q) {
+          Job& J = jobs[j0 + q];
+          id_first_sets(P, J.cand, J.plo, J.pn, J.pf);
+        });
+        std::vector<EntryJob> ej;
+        ej.reserve(static_cast<size_t>(2 * (j1 - j0)));
+        for (int64_t job = j0; job < j1; ++job) {
+          Job& J = jobs[job];
+          const int32_t nc = static_cast<int32_t>(J.cand.size());
+          if (J.pf.samp.empty()) continue;
+          const int32_t sw = J.partner_rows ? 0 : 1;
+          ej.push_back({J.pf.samp.data(), static_cast<int32_t>(J.pf.samp.size()), J.cand.data(), nc, sw,
+                        J.pf.Ms.data()});
+          ej.push_back({J.pf.probe.data(), static_cast<int32_t>(J.pf.probe.size()), J.cand.data(), nc, sw,
+                        J.pf.Mp.data()});
+          J.pf.ready = true;
+        }
+        eval->eval(ej);
+        run_ids(j0, j1, true);
+      }
+    }
     // arena segments and statistics
     for (auto* vec : {&Ccur, &Rcur}) {
       for (auto& r : *vec) {
@@ -523,21 +611,35 @@ void build_level_blocks(Plan& P, int v, double eps, int nthreads) {
       cs.push_back(&Cprev[b * nid + (((2 * sg + 1) << D) + ta)]);
     }
   };
-  parallel_for(nb * nD * nD, nthreads, [&](int64_t job) {
+  const int64_t nmid = nb * nD * nD;
+  std::vector<std::vector<int32_t>> mid_rows(static_cast<size_t>(nmid)), mid_cols(static_cast<size_t>(nmid));
+  parallel_for(nmid, nthreads, [&](int64_t job) {
     const int64_t b = job / (nD * nD);
     const int64_t ta = (job / nD) % nD;
     const int64_t sg = job % nD;
     std::vector<const IdRec*> rs, cs;
     mid_sets(b, ta, sg, rs, cs);
-    std::vector<int32_t> rows, cols;
+    std::vector<int32_t>& rows = mid_rows[job];
+    std::vector<int32_t>& cols = mid_cols[job];
     for (auto* r : rs) rows.insert(rows.end(), r->skel.begin(), r->skel.end());
     for (auto* c : cs) cols.insert(cols.end(), c->skel.begin(), c->skel.end());
     std::vector<cplx>& M = mid_mats[job];
     M.resize(rows.size() * cols.size());
     // column-major n_dst x n_src
-    for (size_t t = 0; t < cols.size(); ++t)
-      for (size_t i = 0; i < rows.size(); ++i) M[t * rows.size() + i] = P.entry(rows[i], cols[t]);
+    if (!eval)
+      for (size_t t = 0; t < cols.size(); ++t)
+        for (size_t i = 0; i < rows.size(); ++i) M[t * rows.size() + i] = P.entry(rows[i], cols[t]);
   });
+  if (eval) {
+    for (int64_t j0 = 0; j0 < nmid; j0 += 8 * kIdBatch) {
+      std::vector<EntryJob> ej;
+      for (int64_t job = j0; job < std::min(nmid, j0 + 8 * kIdBatch); ++job)
+        if (!mid_mats[job].empty())
+          ej.push_back({mid_rows[job].data(), static_cast<int32_t>(mid_rows[job].size()), mid_cols[job].data(),
+                        static_cast<int32_t>(mid_cols[job].size()), 0, mid_mats[job].data()});
+      eval->eval(ej);
+    }
+  }
   for (int64_t b = 0; b < nb; ++b) {
     BlockInfo& bi = P.blocks[b0 + b];
     bi.lvl_begin[D] = static_cast<int32_t>(P.units.size());
@@ -565,7 +667,9 @@ void build_level_blocks(Plan& P, int v, double eps, int nthreads) {
   }
 }
 
-int32_t dense_unit(Plan& P, int64_t r0, int64_t c0, int n0, uint8_t in_buf, uint8_t out_buf) {
+// A dense n0 x n0 block A[r0 + i, c0 + t], M column-major (M[t n0 + i]).
+int32_t dense_block_unit(Plan& P, int64_t r0, int64_t c0, int n0, uint8_t in_buf, uint8_t out_buf,
+                         const std::vector<cplx>& M) {
   Unit u = blank_unit(UNIT_DENSE);
   u.in_buf = in_buf;
   u.out_buf = out_buf;
@@ -573,10 +677,14 @@ int32_t dense_unit(Plan& P, int64_t r0, int64_t c0, int n0, uint8_t in_buf, uint
   u.in_len[0] = static_cast<int16_t>(n0);
   u.out_off[0] = static_cast<int32_t>(r0);
   u.out_len[0] = static_cast<int16_t>(n0);
+  return push_unit(P, u, M, {});
+}
+
+int32_t dense_unit(Plan& P, int64_t r0, int64_t c0, int n0, uint8_t in_buf, uint8_t out_buf) {
   std::vector<cplx> M(static_cast<size_t>(n0) * n0);
   for (int t = 0; t < n0; ++t)
     for (int i = 0; i < n0; ++i) M[static_cast<size_t>(t) * n0 + i] = P.entry(r0 + i, c0 + t);
-  return push_unit(P, u, M, {});
+  return dense_block_unit(P, r0, c0, n0, in_buf, out_buf, M);
 }
 
 Launch make_launch(const Plan& P, int direct, int first, int count, int acc, int kind) {
@@ -640,7 +748,7 @@ cplx Plan::entry(int64_t i, int64_t j) const {
 }
 
 void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double tol,
-                const hbf_build_opts* opts) {
+                const hbf_build_opts* opts, EntryEval* eval) {
   auto t0 = std::chrono::steady_clock::now();
   if (!curve || curve->ncurves < 1 || !curve->node_off || !curve->xy)
     throw std::invalid_argument("hbf_build: empty curve");
@@ -736,21 +844,58 @@ void build_plan(Plan& P, const hbf_curve* curve, double kappa, int leaf, double 
   P.sum_rank = 0;
   P.n_ids = 0;
 
-  // diagonal leaves and the dense L = 0 blocks of the last level
-  P.diag_unit.assign(nl, -1);
-  for (int64_t b = 0; b < nl; ++b) P.diag_unit[b] = dense_unit(P, b * leaf, b * leaf, leaf, BUF_X, BUF_Y);
+  if (eval) eval->prepare(P);
+  // diagonal leaves and the dense L = 0 blocks of the last level, in this order
   const int64_t npl = nl / 2;
+  std::vector<std::pair<int64_t, int64_t>> dense_rc;  // (first row, first column)
+  for (int64_t b = 0; b < nl; ++b) dense_rc.push_back({b * leaf, b * leaf});
+  for (int64_t p = 0; p < npl; ++p) {
+    dense_rc.push_back({(2 * p + 1) * leaf, 2 * p * leaf});
+    dense_rc.push_back({2 * p * leaf, (2 * p + 1) * leaf});
+  }
+  std::vector<int32_t> dense_ids(dense_rc.size(), -1);
+  if (!eval) {
+    for (size_t q = 0; q < dense_rc.size(); ++q)
+      dense_ids[q] = dense_unit(P, dense_rc[q].first, dense_rc[q].second, leaf, BUF_X, BUF_Y);
+  } else {
+    constexpr size_t kDenseBatch = 4096;
+    const size_t bs = static_cast<size_t>(leaf) * leaf;
+    std::vector<int32_t> idx;
+    std::vector<cplx> M;
+    for (size_t q0 = 0; q0 < dense_rc.size(); q0 += kDenseBatch) {
+      const size_t q1 = std::min(dense_rc.size(), q0 + kDenseBatch);
+      idx.assign(2 * leaf * (q1 - q0), 0);
+      M.assign(bs * (q1 - q0), cplx(0.0));
+      std::vector<EntryJob> ej;
+      for (size_t q = q0; q < q1; ++q) {
+        int32_t* rows = &idx[2 * leaf * (q - q0)];
+        int32_t* cols = rows + leaf;
+        for (int i = 0; i < leaf; ++i) {
+          rows[i] = static_cast<int32_t>(dense_rc[q].first + i);
+          cols[i] = static_cast<int32_t>(dense_rc[q].second + i);
+        }
+        ej.push_back({rows, leaf, cols, leaf, 0, &M[bs * (q - q0)]});
+      }
+      eval->eval(ej);
+      for (size_t q = q0; q < q1; ++q) {
+        std::vector<cplx> Mq(M.begin() + bs * (q - q0), M.begin() + bs * (q - q0 + 1));
+        dense_ids[q] = dense_block_unit(P, dense_rc[q].first, dense_rc[q].second, leaf, BUF_X, BUF_Y, Mq);
+      }
+    }
+  }
+  P.diag_unit.assign(nl, -1);
   P.l0_lower_unit.assign(npl, -1);
   P.l0_upper_unit.assign(npl, -1);
+  for (int64_t b = 0; b < nl; ++b) P.diag_unit[b] = dense_ids[b];
   for (int64_t p = 0; p < npl; ++p) {
-    P.l0_lower_unit[p] = dense_unit(P, (2 * p + 1) * leaf, 2 * p * leaf, leaf, BUF_X, BUF_Y);
-    P.l0_upper_unit[p] = dense_unit(P, 2 * p * leaf, (2 * p + 1) * leaf, leaf, BUF_X, BUF_Y);
+    P.l0_lower_unit[p] = dense_ids[nl + 2 * p];
+    P.l0_upper_unit[p] = dense_ids[nl + 2 * p + 1];
   }
   const int64_t dense_end = static_cast<int64_t>(P.fac.size());
   // butterfly blocks, H-level by H-level
   const bool verbose = opts && opts->verbose;
   for (int v = 1; v < P.V; ++v) {
-    build_level_blocks(P, v, eps, nthreads);
+    build_level_blocks(P, v, eps, nthreads, eval);
     if (verbose) {
       const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       std::fprintf(stderr, "[hbf] H-level %d of %d compressed: %zu units, %.2f GB of factors (%.1f s)\n", v, P.V - 1,

@@ -661,13 +661,50 @@ void hbf_hankel2_0(const double* x, int64_t n, double* out) {
   }
 }
 
+namespace {
+// The batched entry interface served on the host (P.entry per element,
+// threads over the jobs): lets the host check build take the same batched
+// path as a device build, so the batching itself is checked without a GPU.
+class HostBatchedEntries final : public hbf::EntryEval {
+ public:
+  explicit HostBatchedEntries(int threads) : threads_(threads) {}
+  void prepare(const hbf::Plan& P) override { P_ = &P; }
+  void eval(const std::vector<hbf::EntryJob>& jobs) override {
+    std::atomic<size_t> next(0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < threads_; ++t)
+      th.emplace_back([&]() {
+        for (;;) {
+          const size_t q = next.fetch_add(1);
+          if (q >= jobs.size()) return;
+          const hbf::EntryJob& J = jobs[q];
+          for (int c = 0; c < J.ncols; ++c)
+            for (int a = 0; a < J.nrows; ++a)
+              J.out[static_cast<size_t>(c) * J.nrows + a] =
+                  J.swap ? P_->entry(J.cols[c], J.rows[a]) : P_->entry(J.rows[a], J.cols[c]);
+        }
+      });
+    for (auto& x : th) x.join();
+  }
+
+ private:
+  int threads_;
+  const hbf::Plan* P_ = nullptr;
+};
+}  // namespace
+
 hbf_status hbf_plan_build(const hbf_curve* curve, double kappa, int32_t leaf, double tol,
                           const hbf_build_opts* opts, hbf_plan** out) {
   if (!out) { set_error("hbf_plan_build: out is NULL"); return HBF_EINVAL; }
   *out = nullptr;
   try {
     auto p = std::make_unique<hbf_plan>();
-    build_plan(p->P, curve, kappa, leaf, tol, opts);
+    if (opts && opts->host_entries == 2) {
+      HostBatchedEntries ev(std::max(1, build_threads(opts)));
+      build_plan(p->P, curve, kappa, leaf, tol, opts, &ev);
+    } else {
+      build_plan(p->P, curve, kappa, leaf, tol, opts);
+    }
     p->prec = opts ? opts->prec : HBF_PREC_BLOCK_LU;
     host_leaf_factor(p->P, p->prec);
     // the device's default sweep schedule: programs over subtrees of 2^5

@@ -29,7 +29,7 @@ def _curve_struct(curves):
 
 
 def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, nthreads=0, eta0=0.0,
-          cache_plan=0, superleaf=0, verbose=0):
+          cache_plan=0, superleaf=0, verbose=0, host_entries=0):
     keep = []
     zp = None
     if z is not None:
@@ -37,7 +37,7 @@ def _opts(dtype="c64", prec="block", z=None, max_nrhs=1, restart=30, device=0, n
         keep.append(zz)
         zp = zz.ctypes.data_as(C.POINTER(C.c_double))
     o = _capi.BuildOpts(DTYPE[dtype], PREC[prec], eta0, zp, max_nrhs, restart, device, nthreads, cache_plan,
-                        superleaf, int(verbose))
+                        superleaf, int(verbose), int(host_entries))
     return o, keep
 
 
@@ -55,14 +55,16 @@ class HostPlan:
     checks; not a compute path of the library)."""
 
     def __init__(self, curves, kappa, leaf, tol, prec="block", z=None, nthreads=0, lib=None, dtype="c128",
-                 superleaf=0):
+                 superleaf=0, batched_entries=False):
+        # batched_entries: evaluate the construction's kernel entries through
+        # the batched interface a device build uses (served on the host)
         # dtype: the device storage type whose sweep schedule the plan mirrors
         # (it sets which sweep programs keep their vectors in LDS); the host
         # evaluation is FP64 either way
         self.lib = lib or _capi.load()
         cs, keep = _curve_struct(curves)
         self._keep = list(keep)
-        o, k2 = _opts(dtype, prec, z, nthreads=nthreads, superleaf=superleaf)
+        o, k2 = _opts(dtype, prec, z, nthreads=nthreads, superleaf=superleaf, host_entries=2 if batched_entries else 0)
         self._keep += k2
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_plan_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))
@@ -115,7 +117,7 @@ class Context:
     device, shape (N,) or (nrhs, N), complex64 or complex128."""
 
     def __init__(self, curves, kappa, leaf, tol, dtype="c64", prec="block", z=None, max_nrhs=1, restart=30,
-                 device=0, nthreads=0, cache_plan=False, superleaf=0, verbose=False):
+                 device=0, nthreads=0, cache_plan=False, superleaf=0, verbose=False, host_entries=False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("hbf.Context needs a HIP device")
@@ -123,7 +125,8 @@ class Context:
         self.device = torch.device("cuda", device)
         cs, keep = _curve_struct(curves)
         o, k2 = _opts(dtype, prec, z, max_nrhs=max_nrhs, restart=restart, device=device, nthreads=nthreads,
-                      cache_plan=int(cache_plan), superleaf=superleaf, verbose=verbose)
+                      cache_plan=int(cache_plan), superleaf=superleaf, verbose=verbose,
+                      host_entries=host_entries)
         h = C.c_void_p()
         check(self.lib, self.lib.hbf_build(C.byref(cs), kappa, leaf, tol, C.byref(o), C.byref(h)))
         del keep, k2

@@ -218,3 +218,21 @@ def test_any_size_entries_and_impedance():
     A = efie.dense_A(rho, w, KAPPA, z=z)
     x = inputs.random_complex(n, 44)
     assert np.linalg.norm(p.apply(x) - A @ x) / np.linalg.norm(A @ x) < 1e-6
+
+
+@pytest.mark.parametrize("geom,n", [("archimedean_spiral", 4096), ("semicircle", 2049)])
+def test_batched_entry_path_reproduces_direct_construction(geom, n):
+    """A device build evaluates the kernel entries of the ID samples and
+    probes, the dense blocks and the middle couplings in batches before the
+    IDs run.  Served on the host, that batched path gives bit for bit the
+    construction of the direct one (same sample and probe sets, same entries,
+    same IDs), so its bookkeeping is checked without a GPU."""
+    c = getattr(inputs, geom)(n)
+    z = inputs.impedance(n, 6)
+    x = inputs.random_complex((2, n), 47)
+    p0 = HostPlan(c, KAPPA, 64, 1e-6, z=z)
+    p1 = HostPlan(c, KAPPA, 64, 1e-6, z=z, batched_entries=True)
+    assert p0.stats["mean_rank"] == p1.stats["mean_rank"] and p0.stats["max_rank"] == p1.stats["max_rank"]
+    for adj in (False, True):
+        assert np.array_equal(p0.apply(x, adjoint=adj), p1.apply(x, adjoint=adj))
+        assert np.array_equal(p0.precond(x, adjoint=adj), p1.precond(x, adjoint=adj))
