@@ -156,7 +156,9 @@ void factor_leaves(hbf_ctx* c, hipStream_t s) {
   const int64_t ns = static_cast<int64_t>(n0) << P.sl;
   const int64_t nsl = P.n / ns;
   const int64_t blk = ns * ns;
-  const int64_t batch = std::min<int64_t>(nsl, 64);
+  // one workgroup factors one super-leaf; a batch of up to 2 GiB of blocks and
+  // workspace (4 blocks per super-leaf) keeps every CU busy
+  const int64_t batch = std::min<int64_t>(nsl, std::max<int64_t>(64, (int64_t(2) << 30) / (4 * blk * 16)));
   SuperleafOut so;
   const int64_t per = static_cast<int64_t>(n0) * n0 * (1 << P.sl) * ((1 << P.sl) + 1) / 2;
   so.per_superleaf = per;
