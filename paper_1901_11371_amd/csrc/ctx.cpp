@@ -124,11 +124,38 @@ void upload_factors(hbf_ctx* c, int64_t begin, int64_t end, hipStream_t s) {
 
 // Exact FP64 diagonal blocks of the super-leaves without z (row-major ns x ns),
 // cached on the host for refactoring.
-void superleaf_entries(hbf_ctx* c) {
+void superleaf_entries(hbf_ctx* c, EntryEval* ev) {
   const Plan& P = c->P;
   const int64_t ns = static_cast<int64_t>(P.n0) << P.sl;
   const int64_t nsl = P.n / ns;
   c->sl_noz.assign(static_cast<size_t>(nsl * ns * ns), cd{0, 0});
+  if (ev) {
+    // row-major blocks: out[i ns + j] = A(S ns + i, S ns + j) is the job's
+    // column-major product with rows = columns = the super-leaf's indices, swapped
+    static_assert(sizeof(cd) == sizeof(cplx), "complex layouts");
+    constexpr int64_t kBatch = 512;
+    std::vector<std::vector<int32_t>> sets(static_cast<size_t>(std::min(nsl, kBatch)));
+    for (int64_t S0 = 0; S0 < nsl; S0 += kBatch) {
+      const int64_t S1 = std::min(nsl, S0 + kBatch);
+      std::vector<EntryJob> jobs;
+      for (int64_t S = S0; S < S1; ++S) {
+        std::vector<int32_t>& v = sets[S - S0];
+        v.resize(static_cast<size_t>(ns));
+        for (int64_t i = 0; i < ns; ++i) v[i] = static_cast<int32_t>(S * ns + i);
+        jobs.push_back({v.data(), static_cast<int32_t>(ns), v.data(), static_cast<int32_t>(ns), 1,
+                        reinterpret_cast<cplx*>(&c->sl_noz[static_cast<size_t>(S * ns * ns)])});
+      }
+      ev->eval(jobs);
+    }
+    if (!P.z.empty())
+      for (int64_t S = 0; S < nsl; ++S)
+        for (int64_t i = 0; i < ns; ++i) {
+          cd& d = c->sl_noz[static_cast<size_t>((S * ns + i) * ns + i)];
+          d.x -= P.z[S * ns + i].real();
+          d.y -= P.z[S * ns + i].imag();
+        }
+    return;
+  }
   const int T = std::max(1, build_threads(nullptr));
   std::vector<std::thread> th;
   std::atomic<int64_t> next(0);
@@ -723,7 +750,15 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
     for (auto& e : c->ev_step) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
     c->workspace_bytes = static_cast<size_t>(std::max<int64_t>(P.arena_rows, 1)) * R * 16 + 5 * vbytes +
                          static_cast<size_t>(nkry + 1) * N * R * c->elt + 4 * vbytes;
-    if (c->prec != HBF_PREC_NONE) superleaf_entries(c.get());
+    if (c->prec != HBF_PREC_NONE) {
+      std::unique_ptr<EntryEval> ev;
+      if (!(opts && opts->host_entries)) {
+        ev = make_device_entry_eval(c->device);
+        ev->prepare(P);
+      }
+      superleaf_entries(c.get(), ev.get());
+      progress("super-leaf blocks evaluated");
+    }
     factor_leaves(c.get(), s);
     progress("leaf blocks factored");
     // release the host copies of the factors

@@ -1,6 +1,8 @@
 // Kernel entries of A = Z + diag(z) (Sec. 3.1) evaluated on the device for the
 // construction: the sample and probe matrices of a batch of IDs, the dense
-// leaf blocks and the middle couplings, one workgroup per index-set product.
+// leaf blocks, the middle couplings and the super-leaf blocks, one workgroup
+// per index-set product.  Off-diagonal entries are evaluated here; the
+// diagonal is the host's own evaluation, uploaded once.
 //
 // H0^(2)(x) = J0(x) - i Y0(x) in FP64 from the classical formulas (the same
 // ones the host evaluation uses): below x = 25 Miller's backward recurrence
@@ -76,24 +78,13 @@ struct Geom {
   const double* cx;
   const double* cy;
   const double* w;
-  const double2* z;       // null: no impedance
+  const double2* self;    // the diagonal A[i, i] as the host evaluates it (self term + z; 1 on padding)
   const uint8_t* ghost;   // null: no padding
   double kappa, eta0;
 };
 
 __device__ double2 entry(const Geom& g, int i, int j) {
-  if (i == j) {
-    if (g.ghost && g.ghost[i]) return make_double2(1.0, 0.0);
-    // closed-form self term of Sec. 3.1
-    const double c = g.kappa * g.eta0 * g.w[i] / 4.0;
-    const double gam = exp(kEulerGammaD);
-    double2 d = make_double2(c, -c * (2.0 / kPiD) * log(gam * g.kappa * g.w[i] / (4.0 * exp(1.0))));
-    if (g.z) {
-      d.x += g.z[i].x;
-      d.y += g.z[i].y;
-    }
-    return d;
-  }
+  if (i == j) return g.self[i];
   if (g.ghost && (g.ghost[i] || g.ghost[j])) return make_double2(0.0, 0.0);
   const double r = hypot(g.cx[i] - g.cx[j], g.cy[i] - g.cy[j]);
   const double2 h = h0(g.kappa * r);
@@ -133,7 +124,7 @@ class DeviceEntries final : public EntryEval {
     check(hipSetDevice(device_), "hipSetDevice");
     if (!stream_) check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "stream");
     const size_t n = static_cast<size_t>(P.n);
-    const size_t bytes = 3 * n * sizeof(double) + (P.z.empty() ? 0 : n * 16) + (P.ghost.empty() ? 0 : n) + 64;
+    const size_t bytes = 3 * n * sizeof(double) + n * 16 + (P.ghost.empty() ? 0 : n) + 64;
     if (geo_) (void)hipFree(geo_);
     geo_ = nullptr;
     check(hipMalloc(&geo_, bytes), "geometry");
@@ -147,12 +138,14 @@ class DeviceEntries final : public EntryEval {
     g_.w = reinterpret_cast<const double*>(p);
     check(hipMemcpy(p, P.w.data(), n * sizeof(double), hipMemcpyHostToDevice), "geometry");
     p += n * sizeof(double);
-    g_.z = nullptr;
-    if (!P.z.empty()) {
-      g_.z = reinterpret_cast<const double2*>(p);
-      check(hipMemcpy(p, P.z.data(), n * 16, hipMemcpyHostToDevice), "impedance");
-      p += n * 16;
-    }
+    // the diagonal from the host's own evaluation, so that it is bit for bit
+    // the one every other part of the library uses (an exactly singular leaf
+    // stays exactly singular)
+    std::vector<cplx> self(n);
+    for (size_t i = 0; i < n; ++i) self[i] = P.self_entry(static_cast<int64_t>(i));
+    g_.self = reinterpret_cast<const double2*>(p);
+    check(hipMemcpy(p, self.data(), n * 16, hipMemcpyHostToDevice), "diagonal");
+    p += n * 16;
     g_.ghost = nullptr;
     if (!P.ghost.empty()) {
       g_.ghost = reinterpret_cast<const uint8_t*>(p);
