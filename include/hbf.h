@@ -90,9 +90,12 @@ typedef struct {
   int32_t superleaf;  /* leaf solves of the sweeps invert diagonal blocks of 2^superleaf leaves
                          exactly (2 or 3; <= 0 selects 2) */
   int32_t verbose;    /* 1: one progress line per construction phase and H-level on stderr */
-  int32_t host_entries; /* hbf_build: 1 = evaluate the construction's kernel entries on the host;
-                           0 (default) = on the device, in batches (the IDs run on the host either
-                           way).  hbf_plan_build: 2 = take the same batched path, served on the host */
+  int32_t host_entries; /* hbf_build: 1 = evaluate the construction's kernel entries and IDs on the
+                           host; 0 (default) = on the device, in batches: the entries of every ID's
+                           first sample and probe, the dense and super-leaf blocks and the middle
+                           couplings, and the column ID of every first sample (the probe checks and
+                           any larger samples stay on the host).  hbf_plan_build: 2 = take the same
+                           batched path, served on the host */
 } hbf_build_opts;
 
 /* Krylov method of the inner solves. */

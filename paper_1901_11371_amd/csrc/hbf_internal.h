@@ -168,6 +168,7 @@ struct Plan {
 
 // A product of index sets whose kernel entries the construction needs:
 // out[c * nrows + a] = swap ? entry(cols[c], rows[a]) : entry(rows[a], cols[c]).
+// out == nullptr: the matrix is only needed by an IdJob and stays with the evaluator.
 struct EntryJob {
   const int32_t* rows;
   int32_t nrows;
@@ -177,15 +178,34 @@ struct EntryJob {
   cplx* out;
 };
 
-// Batched evaluation of kernel entries for the construction: prepare() once
-// the plan's geometry, impedance and padding are final, then any number of
-// eval() calls (each blocking until its outputs are written).
+// The column ID of the matrix of entry job `job` (rows = samples, columns =
+// candidates), computed like column_id: rank *k, pivot order perm (ncols
+// bytes), interpolation matrix T (k x (ncols - k), row-major, at most
+// ncols^2 / 4 entries).
+struct IdJob {
+  int32_t job;
+  int32_t kmax;
+  double eps;
+  int32_t* k;
+  uint8_t* perm;
+  cplx* T;
+};
+
+// Batched evaluation of kernel entries (and optionally of the column IDs of
+// some of the evaluated matrices) for the construction: prepare() once the
+// plan's geometry, impedance and padding are final, then any number of eval()
+// calls (each blocking until its outputs are written).
 class EntryEval {
  public:
   virtual ~EntryEval() = default;
   virtual void prepare(const Plan& P) = 0;
-  virtual void eval(const std::vector<EntryJob>& jobs) = 0;
+  virtual void eval(const std::vector<EntryJob>& jobs, const std::vector<IdJob>& ids) = 0;
+  void eval(const std::vector<EntryJob>& jobs) { eval(jobs, {}); }
 };
+
+// Column ID of the s x n matrix M (column-major, overwritten): k, perm, T as
+// described for IdJob (plan.cpp).
+void column_id_into(std::vector<cplx>& M, int s, int n, double eps, int kmax, int32_t* k, uint8_t* perm, cplx* T);
 
 // The device evaluator (entries.hip): FP64 entries on the given HIP device.
 std::unique_ptr<EntryEval> make_device_entry_eval(int device);

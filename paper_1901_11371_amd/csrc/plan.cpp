@@ -213,6 +213,11 @@ struct IdPrefetch {
   std::vector<int32_t> samp, probe;
   std::vector<cplx> Ms, Mp;
   bool ready = false;
+  // the column ID of the first sample, computed by the evaluator (id_ready)
+  bool id_ready = false;
+  int32_t k = 0;
+  std::vector<uint8_t> perm;
+  std::vector<cplx> T;
 };
 
 uint64_t id_seed(int64_t plo, const std::vector<int32_t>& cand) {
@@ -252,7 +257,6 @@ void id_first_sets(const Plan& P, const std::vector<int32_t>& cand, int64_t plo,
   pf.probe.resize(kProbe);
   for (int a = 0; a < kProbe; ++a) pf.probe[a] = static_cast<int32_t>(id_rnd(seed) % pr);
   to_partner(pf.probe);
-  pf.Ms.resize(pf.samp.size() * n);
   pf.Mp.resize(pf.probe.size() * n);
 }
 
@@ -301,9 +305,17 @@ void compute_id(const Plan& P, const std::vector<int32_t>& cand, int64_t plo, in
     mock_cheb(0, pr, s, samp);
     to_partner(samp);
     const int ss = static_cast<int>(samp.size());
-    if (pf) fill_or_take(samp, M, pf->samp, pf->Ms);
-    else fill(samp, M);
-    column_id(M, ss, n, eps, std::min(n, 127), out);
+    if (pf && pf->id_ready && samp == pf->samp) {
+      // the first sample's ID, computed with its matrix by the evaluator
+      out.k = pf->k;
+      out.perm.swap(pf->perm);
+      out.T.assign(pf->T.begin(), pf->T.begin() + static_cast<size_t>(pf->k) * (n - pf->k));
+      pf->id_ready = false;
+    } else {
+      if (pf) fill_or_take(samp, M, pf->samp, pf->Ms);
+      else fill(samp, M);
+      column_id(M, ss, n, eps, std::min(n, 127), out);
+    }
     if (ss >= pr) break;
     const int need = 2 * out.k + 16;
     if (ss < need) {
@@ -462,19 +474,27 @@ void build_level_blocks(Plan& P, int v, double eps, int nthreads, EntryEval* eva
           id_first_sets(P, J.cand, J.plo, J.pn, J.pf);
         });
         std::vector<EntryJob> ej;
+        std::vector<IdJob> ids;
         ej.reserve(static_cast<size_t>(2 * (j1 - j0)));
+        ids.reserve(static_cast<size_t>(j1 - j0));
         for (int64_t job = j0; job < j1; ++job) {
           Job& J = jobs[job];
           const int32_t nc = static_cast<int32_t>(J.cand.size());
           if (J.pf.samp.empty()) continue;
           const int32_t sw = J.partner_rows ? 0 : 1;
-          ej.push_back({J.pf.samp.data(), static_cast<int32_t>(J.pf.samp.size()), J.cand.data(), nc, sw,
-                        J.pf.Ms.data()});
+          // the first sample's matrix feeds the evaluator's ID only
+          ids.push_back({static_cast<int32_t>(ej.size()), std::min(nc, 127), eps, &J.pf.k, nullptr, nullptr});
+          ej.push_back({J.pf.samp.data(), static_cast<int32_t>(J.pf.samp.size()), J.cand.data(), nc, sw, nullptr});
           ej.push_back({J.pf.probe.data(), static_cast<int32_t>(J.pf.probe.size()), J.cand.data(), nc, sw,
                         J.pf.Mp.data()});
+          J.pf.perm.resize(static_cast<size_t>(nc));
+          J.pf.T.resize(static_cast<size_t>(nc) * nc / 4 + 1);
+          ids.back().perm = J.pf.perm.data();
+          ids.back().T = J.pf.T.data();
           J.pf.ready = true;
+          J.pf.id_ready = true;
         }
-        eval->eval(ej);
+        eval->eval(ej, ids);
         run_ids(j0, j1, true);
       }
     }
@@ -716,6 +736,14 @@ Launch make_launch(const Plan& P, int direct, int first, int count, int acc, int
 }
 
 }  // namespace
+
+void column_id_into(std::vector<cplx>& M, int s, int n, double eps, int kmax, int32_t* k, uint8_t* perm, cplx* T) {
+  IdRec r;
+  column_id(M, s, n, eps, kmax, r);
+  *k = r.k;
+  std::copy(r.perm.begin(), r.perm.end(), perm);
+  std::copy(r.T.begin(), r.T.end(), T);
+}
 
 int32_t add_group(Plan& p, const std::vector<int32_t>& unit_ids) {
   if (p.group_off.empty()) p.group_off.push_back(0);

@@ -669,7 +669,10 @@ class HostBatchedEntries final : public hbf::EntryEval {
  public:
   explicit HostBatchedEntries(int threads) : threads_(threads) {}
   void prepare(const hbf::Plan& P) override { P_ = &P; }
-  void eval(const std::vector<hbf::EntryJob>& jobs) override {
+  void eval(const std::vector<hbf::EntryJob>& jobs, const std::vector<hbf::IdJob>& ids) override {
+    // jobs whose matrices feed an ID (with or without an output pointer)
+    std::vector<int> id_of(jobs.size(), -1);
+    for (size_t q = 0; q < ids.size(); ++q) id_of[static_cast<size_t>(ids[q].job)] = static_cast<int>(q);
     std::atomic<size_t> next(0);
     std::vector<std::thread> th;
     for (int t = 0; t < threads_; ++t)
@@ -678,10 +681,21 @@ class HostBatchedEntries final : public hbf::EntryEval {
           const size_t q = next.fetch_add(1);
           if (q >= jobs.size()) return;
           const hbf::EntryJob& J = jobs[q];
+          std::vector<hbf::cplx> tmp;
+          hbf::cplx* out = J.out;
+          if (!out || id_of[q] >= 0) {
+            tmp.resize(static_cast<size_t>(J.nrows) * J.ncols);
+            out = tmp.data();
+          }
           for (int c = 0; c < J.ncols; ++c)
             for (int a = 0; a < J.nrows; ++a)
-              J.out[static_cast<size_t>(c) * J.nrows + a] =
+              out[static_cast<size_t>(c) * J.nrows + a] =
                   J.swap ? P_->entry(J.cols[c], J.rows[a]) : P_->entry(J.rows[a], J.cols[c]);
+          if (id_of[q] >= 0) {
+            if (J.out) std::copy(tmp.begin(), tmp.end(), J.out);
+            const hbf::IdJob& I = ids[static_cast<size_t>(id_of[q])];
+            hbf::column_id_into(tmp, J.nrows, J.ncols, I.eps, I.kmax, I.k, I.perm, I.T);
+          }
         }
       });
     for (auto& x : th) x.join();
