@@ -242,6 +242,9 @@ hbf_status hbf_impedance_grad(hbf_ctx* ctx, const void* lam, const void* x, int3
  *                   output row of a run of units (default 1; needs mv_direct),
  *   "lane_max_entries"  ... for stages whose units average at most this many
  *                   matrix entries (default 640),
+ *   "lane_scatter_split"  1 = in those stages, a row-ID transfer row that is
+ *                   redundant in both IDs takes two lanes, one per ID's dot
+ *                   product (default 1),
  *   "use_graphs"    1 = replay the preconditioner sweeps and the solvers' steps
  *                   from HIP graphs,
  *   "mfma"          1 = complex64 stage launches with nrhs >= mfma_min_r run

@@ -64,8 +64,10 @@ void free_device(hbf_ctx* c) {
   dfree(c->d_lunits);
   dfree(c->d_lwaves);
   dfree(c->d_lmap);
+  dfree(c->d_lrole);
   c->d_lwaves = nullptr;
   c->d_lmap = nullptr;
+  c->d_lrole = nullptr;
   dfree(c->d_arena);
   dfree(c->d_vin);
   dfree(c->d_vout);
@@ -280,6 +282,107 @@ namespace hbf {
 
 // Build the sweep schedules for the context's settings and upload their step
 // tables and unit copies (throws on allocation or copy failure).
+// Lane tables of the one-RHS forward matvec launches of single units (the
+// direct launches of c->mv_fwd): a wave takes a run of consecutive units
+// whose lanes fill at most 64, or a 64-row slice of a unit of more than 64
+// outputs; lane l of wave w computes the output
+// lmap[64 w + l] = (unit - wfirst[w]) << 8 | row (0xffff: idle) in the role
+// lrole[64 w + l].  With lane_scatter_split, a SCATTER unit whose rows fit one
+// wave gives each row redundant in both IDs two adjacent lanes (the owner runs
+// the first ID's dot product, its partner the second's), so every lane runs at
+// most one loop.  Replaces the context's tables.
+void build_lane_tables(hbf_ctx* c) {
+  const Plan& P = c->P;
+  std::vector<int32_t> lw;
+  std::vector<uint16_t> lm, lr;
+  for (size_t li = 0; li < c->mv_fwd.size(); ++li) {
+    Launch& l = c->mv_fwd[li];
+    l.lw_first = l.lw_count = l.lw_mean = 0;
+    if (!l.direct || l.count <= 0) continue;
+    // the launch's units in order (for launch-order copies: the first unit of
+    // each group of the plan's launch)
+    const Launch& pl = P.mv_fwd[li];
+    auto unit = [&](int32_t u) -> const Unit& {
+      return l.ucopy ? P.units[P.group_units[P.group_off[pl.first + (u - l.first)]]] : P.units[u];
+    };
+    int64_t ent = 0;
+    for (int32_t u = l.first; u < l.first + l.count; ++u) ent += unit(u).mat_len;
+    l.lw_mean = static_cast<int32_t>(ent / l.count);
+    l.lw_first = static_cast<int32_t>(lw.size());
+    auto open_wave = [&](int32_t u) {
+      lw.push_back(u);
+      lm.resize(lw.size() * 64, 0xffff);
+      lr.resize(lw.size() * 64, 0);
+    };
+    std::vector<std::pair<uint16_t, uint16_t>> items;  // (row, role) of one unit
+    int32_t run = -1;  // first unit of the open run (-1: none)
+    int fill = 0;
+    for (int32_t u = l.first; u < l.first + l.count; ++u) {
+      const Unit& U = unit(u);
+      const int n = U.out_len[0] + U.out_len[1];
+      if (n > 64) {
+        for (int o0 = 0; o0 < n; o0 += 64) {
+          open_wave(u);
+          for (int o = o0; o < std::min(n, o0 + 64); ++o) {
+            lm[(lw.size() - 1) * 64 + (o - o0)] = static_cast<uint16_t>(o);
+            lr[(lw.size() - 1) * 64 + (o - o0)] = kLaneWhole;
+          }
+        }
+        run = -1;
+        continue;
+      }
+      items.clear();
+      if (c->lane_scatter_split && U.type == UNIT_SCATTER) {
+        const uint8_t* pp = P.perm.data() + U.perm;
+        for (int o = 0; o < n; ++o) {
+          const bool d0 = pp[o] >= U.k[0], d1 = pp[n + o] >= U.k[1];
+          if (d0 && d1) {
+            items.push_back({static_cast<uint16_t>(o), kLaneSplit | kLaneOwner | kLaneDot0 | kLanePartner});
+            items.push_back({static_cast<uint16_t>(o), kLaneSplit | kLaneDot1});
+          } else {
+            items.push_back({static_cast<uint16_t>(o),
+                             static_cast<uint16_t>(kLaneSplit | kLaneOwner | (d0 ? kLaneDot0 : 0) |
+                                                   (d1 ? kLaneDot1 : 0))});
+          }
+        }
+      }
+      if (items.empty() || items.size() > 64) {
+        items.clear();
+        for (int o = 0; o < n; ++o) items.push_back({static_cast<uint16_t>(o), kLaneWhole});
+      }
+      const int ni = static_cast<int>(items.size());
+      if (run < 0 || fill + ni > 64 || u - run > 255) {
+        run = u;
+        fill = 0;
+        open_wave(u);
+      }
+      for (int i = 0; i < ni; ++i) {
+        const size_t e = (lw.size() - 1) * 64 + fill + i;
+        lm[e] = static_cast<uint16_t>(((u - run) << 8) | items[i].first);
+        uint16_t role = items[i].second;
+        if (role & kLanePartner) role = static_cast<uint16_t>(role | ((fill + i + 1) << 8));  // the next lane
+        lr[e] = role;
+      }
+      fill += ni;
+    }
+    l.lw_count = static_cast<int32_t>(lw.size()) - l.lw_first;
+  }
+  dfree(c->d_lwaves);
+  dfree(c->d_lmap);
+  dfree(c->d_lrole);
+  c->d_lwaves = nullptr;
+  c->d_lmap = nullptr;
+  c->d_lrole = nullptr;
+  dmalloc(&c->d_lwaves, std::max<size_t>(lw.size(), 1) * sizeof(int32_t), "units");
+  dmalloc(&c->d_lmap, std::max<size_t>(lm.size(), 1) * sizeof(uint16_t), "units");
+  dmalloc(&c->d_lrole, std::max<size_t>(lr.size(), 1) * sizeof(uint16_t), "units");
+  if (!lw.empty()) {
+    hip_check(hipMemcpy(c->d_lwaves, lw.data(), lw.size() * sizeof(int32_t), hipMemcpyHostToDevice), "units");
+    hip_check(hipMemcpy(c->d_lmap, lm.data(), lm.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "units");
+    hip_check(hipMemcpy(c->d_lrole, lr.data(), lr.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "units");
+  }
+}
+
 void rebuild_sweeps(hbf_ctx* c, int prog_levels) {
   // LDS-resident programs exist only for the pipelined program kernel
   const int lds_rows = (c->prog_lds && c->prog_pipe)
@@ -396,10 +499,11 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       const int32_t* wf = c->d_lwaves + l.lw_first;
       const uint16_t* lmap = c->d_lmap + static_cast<int64_t>(l.lw_first) * 64;
+      const uint16_t* lrole = c->d_lrole + static_cast<int64_t>(l.lw_first) * 64;
       hipError_t e;
-      if (c->dtype == HBF_C128) e = launch_lanes_c128(a, wf, lmap, l.lw_count, s);
-      else if (vec_c128) e = launch_lanes_c64_hi(a, wf, lmap, l.lw_count, s);
-      else e = launch_lanes_c64(a, wf, lmap, l.lw_count, s);
+      if (c->dtype == HBF_C128) e = launch_lanes_c128(a, wf, lmap, lrole, l.lw_count, s);
+      else if (vec_c128) e = launch_lanes_c64_hi(a, wf, lmap, lrole, l.lw_count, s);
+      else e = launch_lanes_c64(a, wf, lmap, lrole, l.lw_count, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -679,52 +783,8 @@ hbf_status hbf_build(const hbf_curve* curve, double kappa, int32_t leaf, double 
       dmalloc(&c->d_lunits, std::max<size_t>(lu.size(), 1) * sizeof(Unit), "units");
       if (!lu.empty())
         hip_check(hipMemcpy(c->d_lunits, lu.data(), lu.size() * sizeof(Unit), hipMemcpyHostToDevice), "units");
-      // Lane tables of the forward launches of single units: a wave takes a
-      // run of consecutive units whose outputs fill at most 64 lanes, or a
-      // 64-row slice of a larger unit; lane l of wave w computes the output
-      // lmap[64 w + l] = (unit - wfirst[w]) << 8 | row (0xffff: idle).
-      std::vector<int32_t> lw;
-      std::vector<uint16_t> lm;
-      for (Launch& l : c->mv_fwd) {
-        if (!l.direct || l.count <= 0) continue;
-        const std::vector<Unit>& us = l.ucopy ? lu : P.units;
-        int64_t ent = 0;
-        for (int32_t u = l.first; u < l.first + l.count; ++u) ent += us[u].mat_len;
-        l.lw_mean = static_cast<int32_t>(ent / l.count);
-        l.lw_first = static_cast<int32_t>(lw.size());
-        int32_t run = -1;  // first unit of the open run (-1: none)
-        int fill = 0;
-        for (int32_t u = l.first; u < l.first + l.count; ++u) {
-          const int n = us[u].out_len[0] + us[u].out_len[1];
-          if (n > 64) {
-            for (int o0 = 0; o0 < n; o0 += 64) {
-              lw.push_back(u);
-              lm.resize(lw.size() * 64, 0xffff);
-              for (int o = o0; o < std::min(n, o0 + 64); ++o)
-                lm[(lw.size() - 1) * 64 + (o - o0)] = static_cast<uint16_t>(o);
-            }
-            run = -1;
-            continue;
-          }
-          if (run < 0 || fill + n > 64 || u - run > 255) {
-            run = u;
-            fill = 0;
-            lw.push_back(u);
-            lm.resize(lw.size() * 64, 0xffff);
-          }
-          for (int o = 0; o < n; ++o)
-            lm[(lw.size() - 1) * 64 + fill + o] = static_cast<uint16_t>(((u - run) << 8) | o);
-          fill += n;
-        }
-        l.lw_count = static_cast<int32_t>(lw.size()) - l.lw_first;
-      }
-      dmalloc(&c->d_lwaves, std::max<size_t>(lw.size(), 1) * sizeof(int32_t), "units");
-      dmalloc(&c->d_lmap, std::max<size_t>(lm.size(), 1) * sizeof(uint16_t), "units");
-      if (!lw.empty()) {
-        hip_check(hipMemcpy(c->d_lwaves, lw.data(), lw.size() * sizeof(int32_t), hipMemcpyHostToDevice), "units");
-        hip_check(hipMemcpy(c->d_lmap, lm.data(), lm.size() * sizeof(uint16_t), hipMemcpyHostToDevice), "units");
-      }
     }
+    build_lane_tables(c.get());
     progress("factors uploaded");
     rebuild_sweeps(c.get(), c->S.prog_levels);
     progress("sweep schedules built");
@@ -931,6 +991,18 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     (void)hipDeviceSynchronize();
     free_graphs(c);
     c->lane_max_entries = static_cast<int>(value);
+    return HBF_OK;
+  }
+  if (k == "lane_scatter_split") {
+    if (value != 0 && value != 1) return fail(HBF_EINVAL, "hbf_tune: lane_scatter_split must be 0 or 1");
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    c->lane_scatter_split = value != 0;
+    try {
+      build_lane_tables(c);
+    } catch (const std::exception& e) {
+      return fail(HBF_ENOMEM, std::string("hbf_tune: ") + e.what());
+    }
     return HBF_OK;
   }
   if (k == "lane_units" || k == "mv_direct") {

@@ -52,8 +52,10 @@ struct hbf_ctx {
   hbf::Unit* d_lunits = nullptr;  // launch-order unit copies of the direct matvec launches
   int32_t* d_lwaves = nullptr;    // lane-per-output matvec launches: first unit of each wave
   uint16_t* d_lmap = nullptr;     // ... and each lane's unit offset and output row
+  uint16_t* d_lrole = nullptr;    // ... and its role (kLane* bits)
   bool lane_units = true;      // one-RHS forward matvec launches of single units: one lane per output
   int lane_max_entries = 640;  // ... for launches whose units average at most this many matrix entries
+  bool lane_scatter_split = true;  // SCATTER rows redundant in both IDs on two lanes
   std::vector<hbf::Launch> mv_fwd, mv_adj;  // matvec schedules as launched (mv_direct)
   void* d_arena = nullptr;     // skeleton vectors, arena_rows x max_nrhs x 16 bytes
   void* d_vin = nullptr;       // internal-layout vectors, n x max_nrhs x 16 bytes each

@@ -70,13 +70,27 @@ hipError_t launch_prog_pipe_c128(const StageArgs& a, const int32_t* steps, int s
 hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, bool adjoint, hipStream_t s);
 // One right-hand side, forward, launches of single units: one lane per output;
 // wave w covers units from wfirst[w] on, lane l of it the output named by
-// lmap[64 w + l] ((unit offset) << 8 | row; 0xffff idle) (stage_lanes.hip).
-hipError_t launch_lanes_c64(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, int nwaves,
-                            hipStream_t s);
-hipError_t launch_lanes_c64_hi(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, int nwaves,
-                               hipStream_t s);
-hipError_t launch_lanes_c128(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, int nwaves,
-                             hipStream_t s);
+// lmap[64 w + l] ((unit offset) << 8 | row; 0xffff idle) in the role
+// lrole[64 w + l] (kLane* bits below) (stage_lanes.hip).
+hipError_t launch_lanes_c64(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, const uint16_t* lrole,
+                            int nwaves, hipStream_t s);
+hipError_t launch_lanes_c64_hi(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap,
+                               const uint16_t* lrole, int nwaves, hipStream_t s);
+hipError_t launch_lanes_c128(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, const uint16_t* lrole,
+                             int nwaves, hipStream_t s);
+// Lane roles.  Without kLaneSplit the lane computes its output row whole
+// (role kLaneWhole).  A SCATTER row that is redundant in both IDs can be split
+// over two lanes of one wave, each running the dot product of one ID: the
+// owner (kLaneOwner) adds the skeleton entries and the partner's part (lane
+// given in bits 8-13 when kLanePartner is set) and writes the row.
+enum : uint16_t {
+  kLaneDot0 = 1,
+  kLaneDot1 = 2,
+  kLaneOwner = 4,
+  kLaneSplit = 8,
+  kLanePartner = 0x4000,
+  kLaneWhole = kLaneDot0 | kLaneDot1 | kLaneOwner,
+};
 // Wave-per-group variant (4 groups per workgroup, wave_lds bytes of LDS each).
 hipError_t launch_stage_wave_c64(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);
 hipError_t launch_stage_wave_c128(const StageArgs& a, int ngroups, int wave_lds, bool adjoint, hipStream_t s);

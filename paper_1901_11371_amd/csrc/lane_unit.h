@@ -8,6 +8,7 @@
 //   SCATTER (row-ID transfer):     out[p] = sum over the two IDs of in_o[q] if
 //           q = invperm_o[p] < k_o, else sum_j T_o(j, q - k_o) in_o[j];
 //   DENSE:  out[o] = sum_t M(o, t) src[t], column-major.
+// scatter_part computes one lane's part of a SCATTER row split over two lanes.
 #pragma once
 
 #include "kernels.h"
@@ -67,6 +68,43 @@ __device__ __forceinline__ cx<A> unit_output(const Unit& U, int o, const cx<F>* 
   } else {
 #pragma unroll 4
     for (int t = 0; t < f_in; ++t) mac(val, widen<A>(fac[t * f_out + o]), src(t));
+  }
+  return val;
+}
+
+// The part of SCATTER output row o that a lane of role `role` (kLane* bits)
+// computes when the row's two ID dot products may run on two lanes: the owner
+// adds the row's skeleton entries (q < k) of both IDs, and a lane runs the dot
+// product of at most one ID, so the lanes of a wave share one loop.
+template <class F, class A, class SrcF>
+__device__ __forceinline__ cx<A> scatter_part(const Unit& U, int o, int role, const cx<F>* fac_all,
+                                              const uint8_t* perm_all, const SrcF& src) {
+  const int k0 = U.k[0], k1 = U.k[1];
+  const int f_out = U.out_len[0] + U.out_len[1];
+  const uint8_t* pp = perm_all + U.perm;
+  cx<A> val{0, 0};
+  if (role & kLaneOwner) {
+    const int q0 = pp[o], q1 = pp[f_out + o];
+    if (q0 < k0) {
+      const cx<A> v = src(q0);
+      val.x += v.x;
+      val.y += v.y;
+    }
+    if (q1 < k1) {
+      const cx<A> v = src(k0 + q1);
+      val.x += v.x;
+      val.y += v.y;
+    }
+  }
+  if (role & (kLaneDot0 | kLaneDot1)) {
+    const int id = (role & kLaneDot0) ? 0 : 1;
+    const int k = id ? k1 : k0;
+    const int r = f_out - k;
+    const int q = pp[id * f_out + o];
+    const cx<F>* T = fac_all + U.mat + (id ? k0 * (f_out - k0) : 0) + (q - k);
+    const int sbase = id ? k0 : 0;
+#pragma unroll 4
+    for (int j = 0; j < k; ++j) mac(val, widen<A>(T[j * r]), src(sbase + j));
   }
   return val;
 }

@@ -146,6 +146,8 @@ TUNINGS = [
     {"lane_units": 0, "lane_split": 0},
     {"lane_max_entries": 128},
     {"lane_max_entries": 1 << 20},
+    {"lane_scatter_split": 0},
+    {"lane_scatter_split": 0, "lane_max_entries": 1 << 20},
     {"prog_levels": 7},
     {"r1_max_blocks": 2048},
     {"r1_max_blocks": 3, "sweep_pipe_max_r": 8},
