@@ -297,7 +297,7 @@ void build_lane_tables(hbf_ctx* c) {
   std::vector<uint16_t> lm, lr;
   for (size_t li = 0; li < c->mv_fwd.size(); ++li) {
     Launch& l = c->mv_fwd[li];
-    l.lw_first = l.lw_count = l.lw_mean = 0;
+    l.lw_first = l.lw_count = l.lw_mean = l.lw_split = 0;
     if (!l.direct || l.count <= 0) continue;
     // the launch's units in order (for launch-order copies: the first unit of
     // each group of the plan's launch)
@@ -361,6 +361,7 @@ void build_lane_tables(hbf_ctx* c) {
         lm[e] = static_cast<uint16_t>(((u - run) << 8) | items[i].first);
         uint16_t role = items[i].second;
         if (role & kLanePartner) role = static_cast<uint16_t>(role | ((fill + i + 1) << 8));  // the next lane
+        if (role & kLaneSplit) l.lw_split = 1;
         lr[e] = role;
       }
       fill += ni;
@@ -499,7 +500,7 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       const int32_t* wf = c->d_lwaves + l.lw_first;
       const uint16_t* lmap = c->d_lmap + static_cast<int64_t>(l.lw_first) * 64;
-      const uint16_t* lrole = c->d_lrole + static_cast<int64_t>(l.lw_first) * 64;
+      const uint16_t* lrole = l.lw_split ? c->d_lrole + static_cast<int64_t>(l.lw_first) * 64 : nullptr;
       hipError_t e;
       if (c->dtype == HBF_C128) e = launch_lanes_c128(a, wf, lmap, lrole, l.lw_count, s);
       else if (vec_c128) e = launch_lanes_c64_hi(a, wf, lmap, lrole, l.lw_count, s);

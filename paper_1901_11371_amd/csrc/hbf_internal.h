@@ -87,6 +87,7 @@ struct Launch {
   // context's wave tables; lw_count = 0: none)
   int32_t lw_first = 0, lw_count = 0;
   int32_t lw_mean = 0;    // mean matrix entries per unit of the launch
+  int32_t lw_split = 0;   // 1: some lane of those waves has a split role
   // program kept in LDS (lv_rows > 0): its steps index the rewritten unit
   // copies of Sweeps::punits, whose vector segments are LDS rows: the
   // program's rows [prow0, prow0 + prows) of X at [0, prows), of Y at

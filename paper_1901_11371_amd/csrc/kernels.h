@@ -71,7 +71,8 @@ hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, boo
 // One right-hand side, forward, launches of single units: one lane per output;
 // wave w covers units from wfirst[w] on, lane l of it the output named by
 // lmap[64 w + l] ((unit offset) << 8 | row; 0xffff idle) in the role
-// lrole[64 w + l] (kLane* bits below) (stage_lanes.hip).
+// lrole[64 w + l] (kLane* bits below; nullptr: every lane kLaneWhole)
+// (stage_lanes.hip).
 hipError_t launch_lanes_c64(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, const uint16_t* lrole,
                             int nwaves, hipStream_t s);
 hipError_t launch_lanes_c64_hi(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap,

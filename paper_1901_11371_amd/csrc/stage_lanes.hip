@@ -44,10 +44,11 @@ __device__ __forceinline__ cx<A> lane_value(const StageArgs& a, const Unit& U, i
 constexpr int kLaneWaves = 4;  // waves per workgroup
 
 // Wave w takes the units from wfirst[w] on; lmap[64 w + lane] names the
-// lane's output: (unit offset in the run) << 8 | output row, 0xffff = idle;
-// lrole[64 w + lane] its role.  Every lane of the wave takes part in the
-// exchange of split rows' partial sums.
-template <class F, class V, class A>
+// lane's output: (unit offset in the run) << 8 | output row, 0xffff = idle.
+// SPLIT (launches with split SCATTER rows): lrole[64 w + lane] is the lane's
+// role, and every lane of the wave takes part in the exchange of the split
+// rows' partial sums; otherwise every lane computes its row whole.
+template <class F, class V, class A, bool SPLIT>
 __global__ void __launch_bounds__(64 * kLaneWaves) k_stage_lanes(StageArgs a, const int32_t* wfirst,
                                                                 const uint16_t* lmap, const uint16_t* lrole,
                                                                 int nwaves) {
@@ -56,19 +57,22 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_stage_lanes(StageArgs a, co
   const int lane = threadIdx.x & 63;
   const int64_t e = static_cast<int64_t>(w) * 64 + lane;
   const int m = lmap[e];
-  const int role = lrole[e];
+  const int role = SPLIT ? lrole[e] : kLaneWhole;
+  if (!SPLIT && m == 0xffff) return;
   cx<A> val{0, 0};
   Unit U{};
   if (m != 0xffff) {
     U = a.units[uni(wfirst[w]) + (m >> 8)];
     val = lane_value<F, V, A>(a, U, m & 0xff, role);
   }
-  const int from = (role & kLanePartner) ? (role >> 8) & 63 : lane;
-  const A px = __shfl(val.x, from), py = __shfl(val.y, from);
-  if (m == 0xffff || !(role & kLaneOwner)) return;
-  if (role & kLanePartner) {
-    val.x += px;
-    val.y += py;
+  if constexpr (SPLIT) {
+    const int from = (role & kLanePartner) ? (role >> 8) & 63 : lane;
+    const A px = __shfl(val.x, from), py = __shfl(val.y, from);
+    if (m == 0xffff || !(role & kLaneOwner)) return;
+    if (role & kLanePartner) {
+      val.x += px;
+      val.y += py;
+    }
   }
   const int o = m & 0xff;
   V* db = buffer<V>(a, U.out_buf);
@@ -77,13 +81,18 @@ __global__ void __launch_bounds__(64 * kLaneWaves) k_stage_lanes(StageArgs a, co
                      a.alpha_im);
 }
 
+// lrole == nullptr: a launch without split rows
 template <class F, class V, class A>
 hipError_t launch_lanes(const StageArgs& a, const int32_t* wfirst, const uint16_t* lmap, const uint16_t* lrole,
                         int nwaves, hipStream_t s) {
   if (nwaves <= 0) return hipSuccess;
   const unsigned blocks = static_cast<unsigned>((nwaves + kLaneWaves - 1) / kLaneWaves);
-  hipLaunchKernelGGL((k_stage_lanes<F, V, A>), dim3(blocks), dim3(64 * kLaneWaves), 0, s, a, wfirst, lmap, lrole,
-                     nwaves);
+  if (lrole)
+    hipLaunchKernelGGL((k_stage_lanes<F, V, A, true>), dim3(blocks), dim3(64 * kLaneWaves), 0, s, a, wfirst, lmap,
+                       lrole, nwaves);
+  else
+    hipLaunchKernelGGL((k_stage_lanes<F, V, A, false>), dim3(blocks), dim3(64 * kLaneWaves), 0, s, a, wfirst, lmap,
+                       lrole, nwaves);
   return hipGetLastError();
 }
 
