@@ -33,9 +33,7 @@ __device__ __forceinline__ V* buffer(const StageArgs& a, int i) {
 // lane's part of it in its role (kLane* bits).
 template <class F, class V, class A>
 __device__ __forceinline__ cx<A> lane_value(const StageArgs& a, const Unit& U, int o, int role) {
-  const V* sb = buffer<V>(a, U.in_buf);
-  const int len0 = U.in_len[0], off0 = U.in_off[0], off1 = U.in_off[1];
-  auto src = [&](int s) -> cx<A> { return lanes::widen<A>(sb[s < len0 ? off0 + s : off1 + (s - len0)]); };
+  const lanes::Src<V> src{buffer<V>(a, U.in_buf), U.in_off[0], U.in_off[1], U.in_len[0]};
   const cx<F>* fac = reinterpret_cast<const cx<F>*>(a.fac);
   if (role & kLaneSplit) return lanes::scatter_part<F, A>(U, o, role, fac, a.perm, src);
   return lanes::unit_output<F, A>(U, o, fac, a.perm, src);
