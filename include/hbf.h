@@ -252,7 +252,11 @@ hbf_status hbf_impedance_grad(hbf_ctx* ctx, const void* lam, const void* x, int3
  *   "mfma_min_r"    smallest nrhs for the matrix-core stage launches (default 8),
  *   "mfma_tiles"    right-hand sides per wave of the matvec's matrix-core
  *                   launches, in 16-column tiles: 1, 2 or 4 (default 4),
- *   "sweep_mfma_tiles"  the same for the sweeps' stage launches (default 1).
+ *   "sweep_mfma_tiles"  the same for the sweeps' stage launches (default 1),
+ *   "mfma_split_rows"  matrix-core launches of fewer than this many waves
+ *                   (unit groups x RHS chunks) run the 16-row output tiles of
+ *                   a group on parallel waves; bigger ones, or all with 0,
+ *                   take a group's tiles in turn on one wave (default 2048).
  * Unknown keys or out-of-range values return HBF_EINVAL. */
 hbf_status hbf_tune(hbf_ctx* ctx, const char* key, int64_t value);
 

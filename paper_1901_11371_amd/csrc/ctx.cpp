@@ -485,7 +485,14 @@ hipError_t run_launches(hbf_ctx* c, const std::vector<Launch>& L, bool adjoint, 
       a.alpha_im = alpha_im;
       a.src_cap = 0;
       a.ch = 0;
-      const hipError_t e = launch_stage_mfma_c64(a, l.count, sweep ? c->sweep_mfma_tiles : c->mfma_tiles, adj, s);
+      // a launch of few waves (groups x RHS chunks) gives every 16-row output
+      // tile of a group a wave of its own: its chain of dependent steps is
+      // then one tile long; a launch that fills the device keeps one wave per
+      // group, which reads the group's sources once for all its tiles
+      const int tiles = sweep ? c->sweep_mfma_tiles : c->mfma_tiles;
+      const int64_t gw = static_cast<int64_t>(l.count) * ((R + 16 * tiles - 1) / (16 * tiles));
+      const int mtiles = gw < c->mfma_split_rows ? std::max(1, ((adj ? l.max_in : l.max_out) + 15) / 16) : 1;
+      const hipError_t e = launch_stage_mfma_c64(a, l.count, tiles, mtiles, adj, s);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -992,6 +999,13 @@ hbf_status hbf_tune(hbf_ctx* c, const char* key, int64_t value) {
     (void)hipDeviceSynchronize();
     free_graphs(c);
     c->lane_max_entries = static_cast<int>(value);
+    return HBF_OK;
+  }
+  if (k == "mfma_split_rows") {
+    if (value < 0 || value > (int64_t(1) << 30)) return fail(HBF_EINVAL, "hbf_tune: mfma_split_rows out of range");
+    (void)hipDeviceSynchronize();
+    free_graphs(c);
+    c->mfma_split_rows = static_cast<int>(value);
     return HBF_OK;
   }
   if (k == "lane_scatter_split") {

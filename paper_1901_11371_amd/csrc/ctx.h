@@ -39,6 +39,7 @@ struct hbf_ctx {
   int mfma_min_r = 8;
   int mfma_tiles = 4;          // 16-RHS tiles per wave of the matrix-core matvec launches (1, 2, 4)
   int sweep_mfma_tiles = 1;    // ... of the sweeps' matrix-core stage launches
+  int mfma_split_rows = 2048;  // matrix-core launches of fewer waves: one wave per 16-row output tile
   int r1_max_blocks = 0;       // persistent grid size of the stage kernels (0: resident capacity)
 
   // device memory

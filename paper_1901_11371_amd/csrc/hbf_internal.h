@@ -76,6 +76,8 @@ struct Launch {
   int32_t max_src;     // largest source length of any unit in the launch
   int32_t max_dst;
   int32_t max_mat;     // largest matrix (complex entries) of any unit
+  int32_t max_in = 0;  // largest input length (forward orientation) of any unit
+  int32_t max_out = 0; // largest output length (forward orientation) of any unit
   int32_t out_leaf;    // 1 if the launch writes rows of the external vector (uses alpha/beta)
   int32_t kind;        // 0 butterfly/dense, 1 leaf solve
   int32_t prog = 0;    // 1: a sequential program over steps [first, first+count) of the step table

@@ -66,8 +66,11 @@ hipError_t launch_prog_pipe_c128(const StageArgs& a, const int32_t* steps, int s
                                  hipStream_t s);
 // Many right-hand sides with complex64 factors and vectors: one wave per group,
 // complex GEMMs on FP32 matrix cores (stage_mfma.hip).
-// tiles: 16-RHS column tiles per wave (1, 2 or 4)
-hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, bool adjoint, hipStream_t s);
+// tiles: 16-RHS column tiles per wave (1, 2 or 4); mtiles: waves per group
+// and RHS chunk, each taking every mtiles-th 16-row output tile (1: one wave
+// takes them all)
+hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, int mtiles, bool adjoint,
+                                 hipStream_t s);
 // One right-hand side, forward, launches of single units: one lane per output;
 // wave w covers units from wfirst[w] on, lane l of it the output named by
 // lmap[64 w + l] ((unit offset) << 8 | row; 0xffff idle) in the role

@@ -721,6 +721,8 @@ Launch make_launch(const Plan& P, int direct, int first, int count, int acc, int
     const int b = u.out_len[0] + u.out_len[1];
     l.max_src = std::max({l.max_src, a, b});
     l.max_dst = std::max({l.max_dst, a, b});
+    l.max_in = std::max(l.max_in, a);
+    l.max_out = std::max(l.max_out, b);
     l.max_mat = std::max<int32_t>(l.max_mat, u.mat_len);
   };
   l.single = 1;

@@ -176,6 +176,8 @@ struct SweepGen {
       const int a = q.in_len[0] + q.in_len[1], b = q.out_len[0] + q.out_len[1];
       l.max_src = std::max({l.max_src, a, b});
       l.max_dst = std::max({l.max_dst, a, b});
+      l.max_in = std::max(l.max_in, a);
+      l.max_out = std::max(l.max_out, b);
       l.max_mat = std::max<int32_t>(l.max_mat, q.mat_len);
     }
   }
@@ -303,7 +305,7 @@ void build_sweeps(const Plan& P, Sweeps& S, int prog_levels, int lds_rows) {
   d.direct = 1;
   d.first = P.diag_unit.empty() ? 0 : P.diag_unit[0];
   d.count = static_cast<int32_t>(nl);
-  d.max_src = d.max_dst = P.n0;
+  d.max_src = d.max_dst = d.max_in = d.max_out = P.n0;
   d.max_mat = P.n0 * P.n0;
   d.out_leaf = 0;
   d.kind = 0;

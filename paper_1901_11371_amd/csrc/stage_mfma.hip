@@ -17,6 +17,9 @@
 // rows, summed in the accumulators) for NT 16-column tiles of right-hand
 // sides (NT = 1, 2 or 4: 16, 32 or 64 RHS per wave, an execution parameter),
 // one 16-row output tile at a time, 4 source rows per step.
+#include <algorithm>
+#include <cstdint>
+
 #include "kernels.h"
 
 namespace hbf {
@@ -90,15 +93,21 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Wave gt takes group gt / (nrchunks * mtiles), RHS chunk and the output
+// tiles mt0, mt0 + mtiles, ... of that group (mtiles = 1: all of them, one
+// after another; more: the group's 16-row output tiles run on parallel waves,
+// which shortens the dependent chain of a launch of few groups with many rows).
 template <bool ADJ, int kNT>
-__global__ void __launch_bounds__(64 * kMfmaWaves) k_stage_mfma(StageArgs a, int ngroups, int nrchunks) {
+__global__ void __launch_bounds__(64 * kMfmaWaves) k_stage_mfma(StageArgs a, int ngroups, int nrchunks, int mtiles) {
   __shared__ uint8_t s_inv[kMfmaWaves][512];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int gt = blockIdx.x * kMfmaWaves + wave;
-  if (gt >= ngroups * nrchunks) return;
-  const int gi = gt / nrchunks;
-  const int chunk = gt - gi * nrchunks;
+  if (gt >= ngroups * nrchunks * mtiles) return;
+  const int gi = gt / (nrchunks * mtiles);
+  const int rem = gt - gi * nrchunks * mtiles;
+  const int chunk = rem / mtiles;
+  const int mt0 = rem - chunk * mtiles;
   const int g = a.first + gi;
   int q0, q1;
   if (a.direct) {
@@ -127,7 +136,7 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_stage_mfma(StageArgs a, int
   const int lk = lane >> 4;  // A and B: k index within the step; C: row group
   const int ntiles = (nr + 15) >> 4;
 
-  for (int mt = 0; mt * 16 < n_dst; ++mt) {
+  for (int mt = mt0; mt * 16 < n_dst; mt += mtiles) {
     f32x4 acc_re[kNT], acc_im[kNT];
 #pragma unroll
     for (int t = 0; t < kNT; ++t) {
@@ -208,24 +217,29 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_stage_mfma(StageArgs a, int
 }
 
 template <int NT>
-hipError_t launch_nt(const StageArgs& a, int ngroups, bool adjoint, hipStream_t s) {
+hipError_t launch_nt(const StageArgs& a, int ngroups, int mtiles, bool adjoint, hipStream_t s) {
   const int nrchunks = (a.R + 16 * NT - 1) / (16 * NT);
-  const int64_t waves = static_cast<int64_t>(ngroups) * nrchunks;
+  mtiles = std::max(1, mtiles);
+  const int64_t waves = static_cast<int64_t>(ngroups) * nrchunks * mtiles;
+  if (waves > INT32_MAX) return hipErrorInvalidValue;
   const unsigned blocks = static_cast<unsigned>((waves + kMfmaWaves - 1) / kMfmaWaves);
   if (blocks == 0) return hipSuccess;
   if (adjoint)
-    hipLaunchKernelGGL((k_stage_mfma<true, NT>), dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks);
+    hipLaunchKernelGGL((k_stage_mfma<true, NT>), dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks,
+                       mtiles);
   else
-    hipLaunchKernelGGL((k_stage_mfma<false, NT>), dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks);
+    hipLaunchKernelGGL((k_stage_mfma<false, NT>), dim3(blocks), dim3(64 * kMfmaWaves), 0, s, a, ngroups, nrchunks,
+                       mtiles);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, bool adjoint, hipStream_t s) {
-  if (tiles >= 4) return launch_nt<4>(a, ngroups, adjoint, s);
-  if (tiles == 2) return launch_nt<2>(a, ngroups, adjoint, s);
-  return launch_nt<1>(a, ngroups, adjoint, s);
+hipError_t launch_stage_mfma_c64(const StageArgs& a, int ngroups, int tiles, int mtiles, bool adjoint,
+                                 hipStream_t s) {
+  if (tiles >= 4) return launch_nt<4>(a, ngroups, mtiles, adjoint, s);
+  if (tiles == 2) return launch_nt<2>(a, ngroups, mtiles, adjoint, s);
+  return launch_nt<1>(a, ngroups, mtiles, adjoint, s);
 }
 
 }  // namespace hbf

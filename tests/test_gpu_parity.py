@@ -157,6 +157,7 @@ TUNINGS = [
     {"mfma_min_r": 1, "prog_levels": 3, "use_graphs": 0},
     {"mfma_min_r": 1, "mfma_tiles": 1},
     {"mfma_min_r": 1, "mfma_tiles": 2, "mv_direct": 0},
+    {"mfma_min_r": 1, "mfma_split_rows": 0},
 ]
 
 
